@@ -1,0 +1,201 @@
+/*
+ * sabr.h -- C ABI of the MI355X SABR calibration library (libsabr_hip.so).
+ *
+ * What it computes (Fernandez, Ferreiro, Garcia, Leitao, Lopez-Salas,
+ * Vazquez, "Static and dynamic SABR stochastic volatility models:
+ * calibration and option pricing using GPUs"):
+ *   - model implied volatilities of static SABR (Section 2.1: Hagan's
+ *     eq. "haganf", Obloj's eq. "sigma-SABR", the expansion eq. "vola_SABR")
+ *     and dynamic SABR (Section 2.2: eq. "vola_SABRd" with the functional
+ *     parameters of case I, eq. "el_fun_1", or case II, eq. "el_fun_3");
+ *   - the market-fit objective of Section 3 (sum of squared absolute or
+ *     relative errors, eqs. "error_calibrate_individual_relativo" and
+ *     "error_calibrate_relativo");
+ *   - European call prices by the log-Euler Monte Carlo scheme of Section 4
+ *     (eq. "dis_SABRd", estimator eq. "payoff");
+ *   - calibration by synchronous parallel simulated annealing (Section 5,
+ *     Techniques I and II).
+ *
+ * General rules for every entry point
+ *   - Plain C99 types only.  Every host array is owned by the caller and is
+ *     only read during the call; the library copies what it needs before
+ *     returning.  Device memory is owned by the library (or by the caller for
+ *     arrays the caller passes as device pointers, see sabr_objective_batch).
+ *   - A return value < 0 is an error code (SABR_E_*); a human-readable reason
+ *     is kept in the context (sabr_ctx_last_error).  On error no output array
+ *     is written except the status fields of results.
+ *   - A sabr_ctx is used by one host thread at a time.  All GPU work runs on
+ *     the context's stream; blocking calls synchronise that stream before
+ *     they return.
+ *   - Parameter vector x (doubles):
+ *       static         : [alpha, rho, nu]
+ *       dynamic case I : [alpha, rho0, nu0, a, b]
+ *       dynamic case II: [alpha, rho0, nu0, a, b, d_rho, d_nu, q_rho, q_nu]
+ *     with beta appended as a last entry when it is calibrated (beta_free).
+ */
+#ifndef SABR_H
+#define SABR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SABR_OK 0
+#define SABR_E_INVAL (-1)      /* an argument is outside its stated domain */
+#define SABR_E_NOMEM (-2)      /* host or device allocation failed */
+#define SABR_E_BUDGET (-3)     /* the request needs more device memory than the budget */
+#define SABR_E_DEVICE (-4)     /* a HIP call failed (message has the HIP error string) */
+#define SABR_E_INFEASIBLE (-5) /* case II start point violates rho(t) in [-1,1], nu(t) > 0 */
+#define SABR_E_TIMEOUT (-6)    /* a device-side wait exceeded its bound, or poll timed out */
+#define SABR_E_CANCELLED (-7)  /* a served request was cancelled */
+
+typedef enum { SABR_STATIC = 0, SABR_DYN_I = 1, SABR_DYN_II = 2 } sabr_model;
+typedef enum { SABR_F_HAGAN = 0, SABR_F_OBLOJ = 1, SABR_F_EXPANSION = 2 } sabr_formula;
+typedef enum { SABR_OBJ_FORMULA = 0, SABR_OBJ_MC = 1 } sabr_objective;
+typedef enum { SABR_W_ABSOLUTE = 0, SABR_W_RELATIVE = 1 } sabr_weighting;
+typedef enum { SABR_FP64 = 0, SABR_FP32 = 1 } sabr_precision;
+
+/* Market grid Data_market(K_j, f, T_i), i < n_mat, j < m_i (Section 3),
+ * stored by maturity (CSR).  Host arrays.
+ *   T[n_mat]      maturities in years, > 0
+ *   fwd[n_mat]    forward f_i of maturity i (f = S0 exp((r - y) T)), > 0
+ *   disc[n_mat]   discount factor exp(-r T) applied to Monte Carlo prices, > 0
+ *                 (may be NULL for formula objectives: 1 is used)
+ *   offs[n_mat+1] offs[0] = 0, strictly increasing; row i is offs[i]..offs[i+1]-1
+ *   K[n_obs]      strikes (n_obs = offs[n_mat]); > 0 for the formula, >= 0 for MC
+ *   target[n_obs] market vols (formula objective) or prices (MC objective);
+ *                 finite, and > 0 under relative weighting; may be NULL when
+ *                 only model values are wanted. */
+typedef struct {
+    int32_t n_mat;
+    const double *T, *fwd, *disc;
+    const int32_t *offs;
+    const double *K, *target;
+} sabr_market;
+
+/* Model and search box (Sections 2 and 3: beta fixed beforehand or
+ * calibrated; Section 5: the annealing starts from a fixed x0).
+ *   n_par must equal 3 / 5 / 9 (+1 with beta_free) for the model.
+ *   lb[n_par] <= ub[n_par]; rho bounds within [-1, 1]; alpha lb > 0;
+ *   beta (fixed) in [0, 1]; x0[n_par] inside the box, or NULL (box centre). */
+typedef struct {
+    int32_t model;       /* sabr_model */
+    double beta;         /* used when beta_free == 0 */
+    int32_t beta_free;
+    int32_t n_par;
+    const double *lb, *ub, *x0;
+} sabr_problem;
+
+/* Objective: Technique I (formula; static formulas selectable, dynamic
+ * models always use eq. "vola_SABRd") or Technique II (Monte Carlo prices).
+ * precision: SABR_FP64 evaluates every formula in double; SABR_FP32 runs
+ * the bulk of the formula and path arithmetic in float, with double for the
+ * near-the-money z/x(z), the objective sums and the annealing decisions. */
+typedef struct {
+    int32_t kind;        /* sabr_objective */
+    int32_t formula;     /* sabr_formula, static model only */
+    int32_t weighting;   /* sabr_weighting */
+    int32_t precision;   /* sabr_precision */
+} sabr_objspec;
+
+/* Synchronous simulated annealing (Section 5): n_chains Metropolis chains of
+ * chain_len iterations per temperature level, then every chain restarts
+ * from the best current state.  n_iters iterations per chain in total.
+ * T0 <= 0 takes f(x0) (1 if that is not finite and positive).  Level k runs
+ * at T0 * c^(k * chain_len) with c = cooling in (0, 1]; proposals move every
+ * coordinate by h (2u - 1)(ub - lb), h = max(step0 * sqrt(c^(k chain_len)),
+ * step_min), mirrored once at the bound and clamped.  polish != 0 runs a
+ * double-precision compass search from the best state (formula objective
+ * only).  Random words: Philox4x32-10 keyed by seed, counter (chain,
+ * iteration, block, 1). */
+typedef struct {
+    int32_t n_chains, n_iters, chain_len;
+    double T0, cooling, step0, step_min;
+    uint64_t seed;
+    int32_t polish;
+} sabr_sa;
+
+/* Monte Carlo (Section 4): n_paths paths of the log-Euler scheme with
+ * dt = 1/steps_per_year; maturity i is read at step max(1, floor(T_i / dt)).
+ * Normals by Box-Muller from Philox4x32-10 keyed by seed, counter
+ * (path, step/2, 0, 2).  All maturities of a grid share the paths, so the
+ * grid must have a single forward. */
+typedef struct {
+    int64_t n_paths;
+    int32_t steps_per_year;
+    uint64_t seed;
+} sabr_mc;
+
+typedef struct {
+    double x[10];             /* calibrated parameters (n_par used) */
+    double f;                 /* objective at x */
+    double f_before_polish;   /* best objective found by the annealing */
+    int64_t n_evals;          /* objective evaluations (per calibration) */
+    int64_t n_accept;         /* accepted Metropolis moves, all chains */
+    int32_t status;           /* SABR_OK or an error code */
+} sabr_result;
+
+/* One calibration request: its grid, model, objective, annealing schedule
+ * and (for the Monte Carlo objective) path settings. */
+typedef struct {
+    sabr_market market;
+    sabr_problem problem;
+    sabr_objspec obj;
+    sabr_sa sa;
+    sabr_mc mc;
+} sabr_request;
+
+typedef struct sabr_ctx sabr_ctx;
+
+/* Context on HIP device `device`.  hbm_budget_bytes caps the device memory
+ * the library may hold at once (0: no cap).  stream is a hipStream_t (for
+ * example PyTorch's current stream) or NULL for a stream of the library's
+ * own.  Errors: SABR_E_INVAL (bad device), SABR_E_DEVICE. */
+int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx **out);
+void sabr_ctx_destroy(sabr_ctx *ctx);
+/* Text of the last error on this context (never NULL; "" when none). */
+const char *sabr_ctx_last_error(const sabr_ctx *ctx);
+/* Timing of the dominant kernel: with enable != 0 the library brackets each
+ * launch of its main kernel (annealing, objective or path kernel) with HIP
+ * events on the context's stream; sabr_ctx_timing returns the summed event
+ * time and the number of launches since the last reset. */
+int sabr_ctx_enable_timing(sabr_ctx *ctx, int enable);
+int sabr_ctx_timing(sabr_ctx *ctx, int reset, double *kernel_ms, int64_t *launches,
+                    char *kernel_name, size_t name_len);
+
+/* Calibrate n_req independent requests (Section 5, Techniques I and II).
+ * Requests with the formula objective run together in one persistent
+ * annealing launch per (model, formula, precision) group; Monte Carlo
+ * requests run one after the other.  out[n_req] receives one result per
+ * request (out[r].status < 0 for a request that failed validation; the call
+ * then returns SABR_E_INVAL without running anything). */
+int sabr_calibrate(sabr_ctx *ctx, int32_t n_req, const sabr_request *reqs, sabr_result *out);
+
+/* Objective at n_x parameter vectors (Section 3 cost functions).
+ *   X[n_x * n_par] row-major parameter vectors, f[n_x] objective values,
+ *   model[n_x * n_obs] (may be NULL) model vols or prices.
+ *   X, f and model may be host or device pointers (each is classified with
+ *   hipPointerGetAttributes); device arrays stay where they are.
+ *   market.target may be NULL (f is then not written; model must not be NULL).
+ *   mc is read only for the Monte Carlo objective.
+ * Non-finite or non-positive model vols give f = +inf.  Case II parameter
+ * vectors that violate the constraints give f = +inf. */
+int sabr_objective_batch(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem,
+                         const sabr_objspec *obj, const sabr_mc *mc, int64_t n_x,
+                         const double *X, double *f, double *model);
+
+/* Monte Carlo prices (Section 4) of the calls on `market` (targets ignored)
+ * at the parameters problem->x0 (required), with n_paths paths:
+ * price[n_obs] = disc_i * mean(max(F_{M_i} - K, 0)), std_err[n_obs] its
+ * standard error (std_err may be NULL).  Host arrays. */
+int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem,
+                  const sabr_mc *mc, int32_t precision, double *price, double *std_err);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

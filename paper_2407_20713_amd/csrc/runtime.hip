@@ -1,0 +1,1010 @@
+// runtime.hip -- host side of libsabr_hip.so: the C ABI of include/sabr.h.
+//
+// Validates requests, lays the market grids out in device memory (CSR),
+// launches the kernels on the context's stream and copies results back.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sabr.h"
+#include "sabr_kernels.h"
+
+using namespace sabr;
+
+namespace {
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
+}  // namespace
+
+struct sabr_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t held = 0;
+    std::string err;
+    std::vector<DevBuf> bufs;   // reusable device buffers, by slot
+    int n_cu = 0;
+    size_t max_smem = 0;
+    // timing of the dominant kernel
+    bool timing = false;
+    double kernel_ms = 0.0;
+    int64_t launches = 0;
+    std::string kernel_name;
+    std::vector<EventPair> pending;
+    std::vector<EventPair> pool;
+    // pinned staging for host-to-device copies: valid until the next sync
+    unsigned char *stage = nullptr;
+    size_t stage_bytes = 0, stage_used = 0;
+};
+
+namespace {
+
+int fail(sabr_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(sabr_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                   \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(ctx, SABR_E_DEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                        __FILE__, __LINE__);                                                \
+    } while (0)
+
+// Slots of the context's reusable device buffers.
+enum Slot {
+    S_K, S_FWDP, S_BETAP, S_FORMP, S_WGHTP, S_TARGET, S_LFK, S_LKF, S_P1, S_Z, S_Q1, S_Q2, S_SW, S_ROW,
+    S_T, S_FWD, S_BETAM, S_LNF, S_F1, S_OFFS, S_REQ, S_WGREQ, S_SCHED_G, S_SCHED_H, S_CAND, S_BAR,
+    S_BEST, S_ACC, S_ERR, S_EVALS, S_POLREQ, S_X, S_F, S_MODEL, S_MSTEPS, S_MOFFS, S_DISC, S_OBSROW,
+    S_PART, S_PARTQ, S_PRICE, S_SE, S_Y, S_CX, S_CF, S_BX, S_BF, S_FY, S_MCSTATE, S_NSLOTS
+};
+
+int get_buf(sabr_ctx *c, int slot, size_t bytes, void **out) {
+    if (bytes == 0) bytes = 16;
+    if ((int)c->bufs.size() < S_NSLOTS) c->bufs.resize(S_NSLOTS);
+    DevBuf &b = c->bufs[slot];
+    if (b.bytes < bytes) {
+        size_t want = std::max(bytes, b.bytes * 3 / 2);
+        if (c->budget && c->held - b.bytes + want > c->budget) {
+            want = bytes;
+            if (c->held - b.bytes + want > c->budget)
+                return fail(c, SABR_E_BUDGET, "device memory budget exceeded (%zu + %zu > %zu bytes)",
+                            c->held - b.bytes, want, c->budget);
+        }
+        if (b.p) {
+            hipStreamSynchronize(c->stream);
+            hipFree(b.p);
+            c->held -= b.bytes;
+            b.p = nullptr;
+            b.bytes = 0;
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, want) != hipSuccess) {
+            hipGetLastError();
+            return fail(c, SABR_E_NOMEM, "hipMalloc of %zu bytes failed", want);
+        }
+        b.p = p;
+        b.bytes = want;
+        c->held += want;
+    }
+    *out = b.p;
+    return SABR_OK;
+}
+
+// Asynchronous host-to-device copy through the context's pinned staging
+// buffer, so that the caller's host memory may be released at once.
+int copy_h2d(sabr_ctx *c, void *dst, const void *src, size_t bytes) {
+    if (bytes == 0) return SABR_OK;
+    const size_t need = (bytes + 255) / 256 * 256;
+    if (c->stage_used + need > c->stage_bytes) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->stage_used = 0;
+        if (need > c->stage_bytes) {
+            if (c->stage) hipHostFree(c->stage);
+            c->stage = nullptr;
+            c->stage_bytes = 0;
+            const size_t want = std::max<size_t>(need, 1 << 20);
+            void *h = nullptr;
+            if (hipHostMalloc(&h, want, hipHostMallocDefault) != hipSuccess) {
+                hipGetLastError();
+                return fail(c, SABR_E_NOMEM, "hipHostMalloc of %zu bytes failed", want);
+            }
+            c->stage = static_cast<unsigned char *>(h);
+            c->stage_bytes = want;
+        }
+    }
+    unsigned char *h = c->stage + c->stage_used;
+    std::memcpy(h, src, bytes);
+    c->stage_used += need;
+    HIPCHK(c, hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, c->stream));
+    return SABR_OK;
+}
+
+template <typename T>
+int upload(sabr_ctx *c, int slot, const std::vector<T> &v, T **out) {
+    void *p;
+    int rc = get_buf(c, slot, v.size() * sizeof(T), &p);
+    if (rc) return rc;
+    if ((rc = copy_h2d(c, p, v.data(), v.size() * sizeof(T)))) return rc;
+    *out = static_cast<T *>(p);
+    return SABR_OK;
+}
+
+EventPair take_events(sabr_ctx *c) {
+    EventPair e;
+    if (!c->pool.empty()) {
+        e = c->pool.back();
+        c->pool.pop_back();
+    } else {
+        hipEventCreate(&e.a);
+        hipEventCreate(&e.b);
+    }
+    return e;
+}
+
+// Launch `fn` bracketed by timing events when timing is on.
+int launch(sabr_ctx *c, bool dominant, const char *name, const void *fn, dim3 grid, dim3 block,
+           void **args, size_t smem, bool cooperative = false) {
+    EventPair ev;
+    const bool t = c->timing && dominant;
+    if (t) {
+        ev = take_events(c);
+        HIPCHK(c, hipEventRecord(ev.a, c->stream));
+    }
+    hipError_t e = cooperative ? hipLaunchCooperativeKernel(fn, grid, block, args, (unsigned)smem, c->stream)
+                               : hipLaunchKernel(fn, grid, block, args, smem, c->stream);
+    if (e != hipSuccess) {
+        hipGetLastError();
+        return fail(c, SABR_E_DEVICE, "launch of %s failed: %s", name, hipGetErrorString(e));
+    }
+    if (t) {
+        HIPCHK(c, hipEventRecord(ev.b, c->stream));
+        c->pending.push_back(ev);
+        c->kernel_name = name;
+    }
+    return SABR_OK;
+}
+
+int sync_and_account(sabr_ctx *c) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->stage_used = 0;
+    for (auto &ev : c->pending) {
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, ev.a, ev.b);
+        c->kernel_ms += ms;
+        c->launches += 1;
+        c->pool.push_back(ev);
+    }
+    c->pending.clear();
+    return SABR_OK;
+}
+
+int set_smem(sabr_ctx *c, const void *fn, size_t smem) {
+    if (smem > c->max_smem)
+        return fail(c, SABR_E_INVAL, "market grid needs %zu bytes of LDS, the device has %zu", smem,
+                    c->max_smem);
+    if (smem > 65536) HIPCHK(c, hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    return SABR_OK;
+}
+
+int base_npar(int model) { return model == SABR_STATIC ? 3 : (model == SABR_DYN_I ? 5 : (model == SABR_DYN_II ? 9 : -1)); }
+
+int n_steps(double T, int spy) {
+    const int m = (int)std::floor(T * (double)spy + 1e-9);
+    return m < 1 ? 1 : m;
+}
+
+bool finite(double v) { return std::isfinite(v); }
+
+// --- validation ---------------------------------------------------------------
+int check_market(sabr_ctx *c, const sabr_market *m, bool need_target, bool mc, int weighting) {
+    if (!m) return fail(c, SABR_E_INVAL, "market is NULL");
+    if (m->n_mat < 1) return fail(c, SABR_E_INVAL, "n_mat must be >= 1");
+    if (!m->T || !m->fwd || !m->offs || !m->K) return fail(c, SABR_E_INVAL, "market arrays must not be NULL");
+    if (m->offs[0] != 0) return fail(c, SABR_E_INVAL, "offs[0] must be 0");
+    for (int i = 0; i < m->n_mat; ++i) {
+        if (m->offs[i + 1] <= m->offs[i]) return fail(c, SABR_E_INVAL, "offs must be strictly increasing");
+        if (!(m->T[i] > 0) || !finite(m->T[i])) return fail(c, SABR_E_INVAL, "T[%d] must be > 0", i);
+        if (!(m->fwd[i] > 0) || !finite(m->fwd[i])) return fail(c, SABR_E_INVAL, "fwd[%d] must be > 0", i);
+        if (m->disc && (!(m->disc[i] > 0) || !finite(m->disc[i])))
+            return fail(c, SABR_E_INVAL, "disc[%d] must be > 0", i);
+    }
+    const int n = m->offs[m->n_mat];
+    for (int j = 0; j < n; ++j) {
+        if (!finite(m->K[j]) || (mc ? m->K[j] < 0 : !(m->K[j] > 0)))
+            return fail(c, SABR_E_INVAL, "K[%d] out of range", j);
+        if (m->target) {
+            if (!finite(m->target[j])) return fail(c, SABR_E_INVAL, "target[%d] not finite", j);
+            if (weighting == SABR_W_RELATIVE && !(m->target[j] > 0))
+                return fail(c, SABR_E_INVAL, "target[%d] must be > 0 under relative weighting", j);
+        }
+    }
+    if (need_target && !m->target) return fail(c, SABR_E_INVAL, "market target is NULL");
+    if (mc)
+        for (int i = 1; i < m->n_mat; ++i)
+            if (m->fwd[i] != m->fwd[0])
+                return fail(c, SABR_E_INVAL, "Monte Carlo needs one forward for all maturities");
+    return SABR_OK;
+}
+
+int check_problem(sabr_ctx *c, const sabr_problem *p, bool need_box) {
+    if (!p) return fail(c, SABR_E_INVAL, "problem is NULL");
+    const int np = base_npar(p->model);
+    if (np < 0) return fail(c, SABR_E_INVAL, "unknown model %d", p->model);
+    if (p->n_par != np + (p->beta_free ? 1 : 0))
+        return fail(c, SABR_E_INVAL, "n_par %d does not match model %d (beta_free %d)", p->n_par, p->model,
+                    p->beta_free);
+    if (!p->beta_free && !(p->beta >= 0.0 && p->beta <= 1.0)) return fail(c, SABR_E_INVAL, "beta must be in [0,1]");
+    if (need_box) {
+        if (!p->lb || !p->ub) return fail(c, SABR_E_INVAL, "lb/ub must not be NULL");
+        for (int k = 0; k < p->n_par; ++k) {
+            if (!finite(p->lb[k]) || !finite(p->ub[k]) || p->lb[k] > p->ub[k])
+                return fail(c, SABR_E_INVAL, "box coordinate %d invalid", k);
+            if (p->x0 && !(p->x0[k] >= p->lb[k] && p->x0[k] <= p->ub[k]))
+                return fail(c, SABR_E_INVAL, "x0[%d] outside the box", k);
+        }
+        if (!(p->lb[0] > 0)) return fail(c, SABR_E_INVAL, "alpha lower bound must be > 0");
+        if (p->lb[1] < -1.0 || p->ub[1] > 1.0) return fail(c, SABR_E_INVAL, "rho bounds must lie in [-1, 1]");
+        if (p->lb[2] < 0.0) return fail(c, SABR_E_INVAL, "nu lower bound must be >= 0");
+        if (p->beta_free && (p->lb[p->n_par - 1] < 0.0 || p->ub[p->n_par - 1] > 1.0))
+            return fail(c, SABR_E_INVAL, "beta bounds must lie in [0, 1]");
+    }
+    return SABR_OK;
+}
+
+int check_obj(sabr_ctx *c, const sabr_objspec *o, int model) {
+    if (!o) return fail(c, SABR_E_INVAL, "objspec is NULL");
+    if (o->kind != SABR_OBJ_FORMULA && o->kind != SABR_OBJ_MC) return fail(c, SABR_E_INVAL, "bad objective kind");
+    if (o->formula < 0 || o->formula > 2) return fail(c, SABR_E_INVAL, "bad formula");
+    if (o->weighting != SABR_W_ABSOLUTE && o->weighting != SABR_W_RELATIVE) return fail(c, SABR_E_INVAL, "bad weighting");
+    if (o->precision != SABR_FP64 && o->precision != SABR_FP32) return fail(c, SABR_E_INVAL, "bad precision");
+    (void)model;
+    return SABR_OK;
+}
+
+int check_mc(sabr_ctx *c, const sabr_mc *m) {
+    if (!m) return fail(c, SABR_E_INVAL, "mc settings are NULL");
+    if (m->n_paths < 1 || m->n_paths > (int64_t)0xffffffffLL) return fail(c, SABR_E_INVAL, "n_paths must be in [1, 2^32)");
+    if (m->steps_per_year < 1) return fail(c, SABR_E_INVAL, "steps_per_year must be >= 1");
+    return SABR_OK;
+}
+
+int check_sa(sabr_ctx *c, const sabr_sa *s) {
+    if (s->n_chains < 1 || s->n_iters < 1 || s->chain_len < 1) return fail(c, SABR_E_INVAL, "annealing sizes must be >= 1");
+    if (!(s->cooling > 0.0 && s->cooling <= 1.0)) return fail(c, SABR_E_INVAL, "cooling must be in (0, 1]");
+    if (!(s->step0 > 0.0) || !(s->step_min >= 0.0)) return fail(c, SABR_E_INVAL, "step sizes invalid");
+    return SABR_OK;
+}
+
+bool case2_ok_host(const double *x, double tmax) {
+    auto range = [&](double c0, double c1, double k, double d, double &lo, double &hi) {
+        const double v0 = c0 + d, v1 = (c0 + c1 * tmax) * std::exp(-k * tmax) + d;
+        lo = std::min(v0, v1);
+        hi = std::max(v0, v1);
+        if (k > 0.0 && c1 != 0.0) {
+            const double ts = 1.0 / k - c0 / c1;
+            if (ts > 0.0 && ts < tmax) {
+                const double v = (c0 + c1 * ts) * std::exp(-k * ts) + d;
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+        }
+    };
+    double rlo, rhi, nlo, nhi;
+    range(x[1], x[7], x[3], x[5], rlo, rhi);
+    range(x[2], x[8], x[4], x[6], nlo, nhi);
+    return rlo >= -1.0 && rhi <= 1.0 && nlo > 0.0;
+}
+
+// --- grid packing ---------------------------------------------------------------
+struct Packed {
+    std::vector<double> K, fwdp, betap, target, T, fwd, betam;
+    std::vector<int32_t> formp, wghtp, row, offs;
+};
+
+// Append one grid; returns the point and maturity offsets.
+void pack_grid(Packed &pk, const sabr_market &m, const sabr_problem &p, const sabr_objspec &o, int &pt_off,
+               int &mat_off) {
+    pt_off = (int)pk.K.size();
+    mat_off = (int)pk.T.size();
+    const double beta = p.beta_free ? 1.0 : p.beta;
+    for (int i = 0; i < m.n_mat; ++i) {
+        pk.T.push_back(m.T[i]);
+        pk.fwd.push_back(m.fwd[i]);
+        pk.betam.push_back(beta);
+        pk.offs.push_back(pt_off + m.offs[i]);
+        for (int j = m.offs[i]; j < m.offs[i + 1]; ++j) {
+            pk.K.push_back(m.K[j]);
+            pk.fwdp.push_back(m.fwd[i]);
+            pk.betap.push_back(beta);
+            pk.formp.push_back(o.formula);
+            pk.wghtp.push_back(o.weighting);
+            pk.target.push_back(m.target ? m.target[j] : 0.0);
+            pk.row.push_back(mat_off + i);
+        }
+    }
+}
+
+struct DevGrid {
+    PointsD P;
+    MatsD Mt;
+};
+
+// Upload packed grids and run the normalisation kernels.
+int upload_grids(sabr_ctx *c, Packed &pk, DevGrid &g) {
+    pk.offs.push_back((int32_t)pk.K.size());   // closing offset of the last grid
+    double *K, *fwdp, *betap, *target, *T, *fwd, *betam;
+    int32_t *formp, *wghtp, *row, *offs;
+    int rc;
+    if ((rc = upload(c, S_K, pk.K, &K)) || (rc = upload(c, S_FWDP, pk.fwdp, &fwdp)) ||
+        (rc = upload(c, S_BETAP, pk.betap, &betap)) || (rc = upload(c, S_TARGET, pk.target, &target)) ||
+        (rc = upload(c, S_T, pk.T, &T)) || (rc = upload(c, S_FWD, pk.fwd, &fwd)) ||
+        (rc = upload(c, S_BETAM, pk.betam, &betam)) || (rc = upload(c, S_FORMP, pk.formp, &formp)) ||
+        (rc = upload(c, S_WGHTP, pk.wghtp, &wghtp)) || (rc = upload(c, S_ROW, pk.row, &row)) ||
+        (rc = upload(c, S_OFFS, pk.offs, &offs)))
+        return rc;
+    const size_t np = pk.K.size(), nm = pk.T.size();
+    void *lfk, *lkf, *P1, *Z, *Q1, *Q2, *sw, *lnf, *F1;
+    if ((rc = get_buf(c, S_LFK, np * 8, &lfk)) || (rc = get_buf(c, S_LKF, np * 8, &lkf)) ||
+        (rc = get_buf(c, S_P1, np * 8, &P1)) || (rc = get_buf(c, S_Z, np * 8, &Z)) ||
+        (rc = get_buf(c, S_Q1, np * 8, &Q1)) || (rc = get_buf(c, S_Q2, np * 8, &Q2)) ||
+        (rc = get_buf(c, S_SW, np * 8, &sw)) || (rc = get_buf(c, S_LNF, nm * 8, &lnf)) ||
+        (rc = get_buf(c, S_F1, nm * 8, &F1)))
+        return rc;
+    int n = (int)np;
+    void *a1[] = {&n, &K, &fwdp, &betap, &formp, &wghtp, &target, &lfk, &lkf, &P1, &Z, &Q1, &Q2, &sw};
+    if ((rc = launch(c, false, "prepare_points", prepare_points_kernel_ptr(), dim3((n + 255) / 256), dim3(256), a1, 0)))
+        return rc;
+    int nmi = (int)nm;
+    void *a2[] = {&nmi, &fwd, &betam, &lnf, &F1};
+    if ((rc = launch(c, false, "prepare_mats", prepare_mats_kernel_ptr(), dim3((nmi + 255) / 256), dim3(256), a2, 0)))
+        return rc;
+    g.P = PointsD{(const double *)lfk, (const double *)lkf, (const double *)P1, (const double *)Z,
+                  (const double *)Q1, (const double *)Q2, target, (const double *)sw, row};
+    g.Mt = MatsD{T, (const double *)lnf, (const double *)F1, offs};
+    return SABR_OK;
+}
+
+void fill_desc(ReqDesc &d, const sabr_market &m, const sabr_problem &p, const sabr_objspec &o, int pt_off,
+               int mat_off) {
+    std::memset(&d, 0, sizeof d);
+    d.model = p.model;
+    d.formula = p.model == SABR_STATIC ? o.formula : F_HAGAN;
+    d.weighting = o.weighting;
+    d.beta_free = p.beta_free ? 1 : 0;
+    d.n_par = p.n_par;
+    d.n_mat = m.n_mat;
+    d.n_pts = m.offs[m.n_mat];
+    d.pt_off = pt_off;
+    d.mat_off = mat_off;
+    d.beta = p.beta;
+    double tmax = 0;
+    for (int i = 0; i < m.n_mat; ++i) tmax = std::max(tmax, m.T[i]);
+    d.t_max = tmax;
+    for (int k = 0; k < p.n_par && p.lb; ++k) {
+        d.lb[k] = p.lb[k];
+        d.ub[k] = p.ub[k];
+        d.x0[k] = p.x0 ? p.x0[k] : 0.5 * (p.lb[k] + p.ub[k]);
+    }
+}
+
+bool is_device_ptr(const void *p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof a);
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// --- formula calibration ------------------------------------------------------------
+struct Group {
+    int model, formula, fp32, bfree;
+    std::vector<int> reqs;
+};
+
+int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, sabr_result *out) {
+    const int nr = (int)grp.reqs.size();
+    Packed pk;
+    std::vector<ReqDesc> desc(nr);
+    std::vector<double> sg, sh;
+    std::vector<int32_t> wg_req;
+    int cand_slots = 0;
+    for (int r = 0; r < nr; ++r) {
+        const sabr_request &q = reqs[grp.reqs[r]];
+        int pt_off, mat_off;
+        pack_grid(pk, q.market, q.problem, q.obj, pt_off, mat_off);
+        ReqDesc &d = desc[r];
+        fill_desc(d, q.market, q.problem, q.obj, pt_off, mat_off);
+        d.n_chains = q.sa.n_chains;
+        d.n_iters = q.sa.n_iters;
+        d.chain_len = q.sa.chain_len;
+        d.n_levels = (q.sa.n_iters + q.sa.chain_len - 1) / q.sa.chain_len;
+        d.sched_off = (int)sg.size();
+        d.polish = q.sa.polish;
+        d.key0 = (uint32_t)(q.sa.seed & 0xffffffffu);
+        d.key1 = (uint32_t)(q.sa.seed >> 32);
+        d.T0 = q.sa.T0;
+        const double cL = std::pow(q.sa.cooling, (double)q.sa.chain_len);
+        double g = 1.0;
+        for (int k = 0; k < d.n_levels; ++k) {
+            sg.push_back(g);
+            sh.push_back(std::fmax(q.sa.step0 * std::sqrt(g), q.sa.step_min));
+            g = g * cL;
+        }
+        d.n_wg = (q.sa.n_chains + kWG - 1) / kWG;
+        d.wg_first = (int)wg_req.size();
+        for (int w = 0; w < d.n_wg; ++w) wg_req.push_back(r);
+        d.cand_off = cand_slots;
+        cand_slots += 2 * d.n_wg;
+    }
+    int rc;
+    DevGrid g;
+    if ((rc = upload_grids(c, pk, g))) return rc;
+    ReqDesc *dreq;
+    int32_t *dwg;
+    double *dsg, *dsh;
+    if ((rc = upload(c, S_REQ, desc, &dreq)) || (rc = upload(c, S_WGREQ, wg_req, &dwg)) ||
+        (rc = upload(c, S_SCHED_G, sg, &dsg)) || (rc = upload(c, S_SCHED_H, sh, &dsh)))
+        return rc;
+    void *cand, *bar, *best, *acc, *err, *evals;
+    if ((rc = get_buf(c, S_CAND, sizeof(Cand) * std::max(cand_slots, 1), &cand)) ||
+        (rc = get_buf(c, S_BAR, sizeof(uint32_t) * nr, &bar)) ||
+        (rc = get_buf(c, S_BEST, sizeof(ChainOut) * nr, &best)) ||
+        (rc = get_buf(c, S_ACC, sizeof(unsigned long long) * nr, &acc)) ||
+        (rc = get_buf(c, S_ERR, sizeof(int32_t), &err)) ||
+        (rc = get_buf(c, S_EVALS, sizeof(unsigned long long) * nr, &evals)))
+        return rc;
+    HIPCHK(c, hipMemsetAsync(bar, 0, sizeof(uint32_t) * nr, c->stream));
+    HIPCHK(c, hipMemsetAsync(acc, 0, sizeof(unsigned long long) * nr, c->stream));
+    HIPCHK(c, hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(evals, 0, sizeof(unsigned long long) * nr, c->stream));
+
+    const bool fp32 = grp.fp32 != 0;
+    size_t smem = 0;
+    for (int r = 0; r < nr; ++r) smem = std::max(smem, grid_smem_bytes(fp32, desc[r].n_pts, desc[r].n_mat));
+    smem += sa_smem_fixed_bytes();
+    const void *fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0);
+    if (!fn) return fail(c, SABR_E_INVAL, "no kernel for model %d formula %d", grp.model, grp.formula);
+    if ((rc = set_smem(c, fn, smem))) return rc;
+    const int n_blocks = (int)wg_req.size();
+    bool multi_wg = false;
+    for (int r = 0; r < nr; ++r) multi_wg |= desc[r].n_wg > 1;
+    if (multi_wg) {
+        int per_cu = 0;
+        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWG, smem));
+        if ((int64_t)per_cu * c->n_cu < n_blocks)
+            return fail(c, SABR_E_BUDGET,
+                        "%d annealing workgroups cannot be resident at once (%d per CU x %d CUs); split the batch",
+                        n_blocks, per_cu, c->n_cu);
+    }
+    PointsD P = g.P;
+    MatsD Mt = g.Mt;
+    void *args[] = {&dreq, &dwg, &P, &Mt, &dsg, &dsh, &cand, &bar, &best, &acc, &err};
+    if ((rc = launch(c, true, "sa_kernel", fn, dim3(n_blocks), dim3(kWG), args, smem, multi_wg))) return rc;
+
+    std::vector<ChainOut> hpre(nr);
+    HIPCHK(c, hipMemcpyAsync(hpre.data(), best, sizeof(ChainOut) * nr, hipMemcpyDeviceToHost, c->stream));
+    // polish
+    std::vector<int32_t> pol;
+    for (int r = 0; r < nr; ++r)
+        if (desc[r].polish) pol.push_back(r);
+    if (!pol.empty()) {
+        int32_t *dpol;
+        if ((rc = upload(c, S_POLREQ, pol, &dpol))) return rc;
+        size_t psm = 0;
+        for (int r : pol) psm = std::max(psm, grid_smem_bytes(false, desc[r].n_pts, desc[r].n_mat));
+        const void *pf = polish_kernel_ptr(grp.model, grp.formula, grp.bfree != 0);
+        if ((rc = set_smem(c, pf, psm))) return rc;
+        void *pargs[] = {&dreq, &dpol, &P, &Mt, &best, &evals};
+        if ((rc = launch(c, false, "polish_kernel", pf, dim3((unsigned)pol.size()), dim3(64), pargs, psm))) return rc;
+    }
+    std::vector<ChainOut> hb(nr);
+    std::vector<unsigned long long> ha(nr), he(nr);
+    int32_t herr = 0;
+    HIPCHK(c, hipMemcpyAsync(hb.data(), best, sizeof(ChainOut) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ha.data(), acc, sizeof(unsigned long long) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(he.data(), evals, sizeof(unsigned long long) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync_and_account(c))) return rc;
+    if (herr) return fail(c, SABR_E_TIMEOUT, "a workgroup of the annealing kernel exceeded its wait bound");
+    for (int r = 0; r < nr; ++r) {
+        sabr_result &o = out[grp.reqs[r]];
+        std::memset(&o, 0, sizeof o);
+        for (int k = 0; k < desc[r].n_par; ++k) o.x[k] = hb[r].bx[k];
+        o.f = hb[r].bf;
+        o.f_before_polish = hpre[r].bf;
+        o.n_accept = (int64_t)ha[r];
+        o.n_evals = 1 + (int64_t)desc[r].n_chains * desc[r].n_iters + (int64_t)he[r];
+        o.status = SABR_OK;
+    }
+    return SABR_OK;
+}
+
+// --- Monte Carlo objective ----------------------------------------------------------
+struct McGrid {
+    int n_mat, n_obs, m_max;
+    double t_max;
+    int32_t *msteps, *moffs, *obsrow;
+    double *K, *disc, *target, *sw;
+};
+
+int upload_mc_grid(sabr_ctx *c, const sabr_market &m, int spy, int weighting, McGrid &g) {
+    std::vector<int32_t> ms(m.n_mat), mo(m.n_mat + 1), orow(m.offs[m.n_mat]);
+    std::vector<double> K(m.offs[m.n_mat]), disc(m.n_mat), tg(m.offs[m.n_mat]), sw(m.offs[m.n_mat]);
+    // rows sorted by step so that the kernels meet the maturities in order
+    std::vector<int> order(m.n_mat);
+    for (int i = 0; i < m.n_mat; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n_steps(m.T[a], spy) < n_steps(m.T[b], spy); });
+    bool sorted = true;
+    for (int i = 0; i < m.n_mat; ++i) sorted &= order[i] == i;
+    if (!sorted) return fail(c, SABR_E_INVAL, "Monte Carlo grids must list maturities in increasing order");
+    g.m_max = 0;
+    for (int i = 0; i < m.n_mat; ++i) {
+        ms[i] = n_steps(m.T[i], spy);
+        g.m_max = std::max(g.m_max, ms[i]);
+        mo[i] = m.offs[i];
+        disc[i] = m.disc ? m.disc[i] : 1.0;
+        for (int j = m.offs[i]; j < m.offs[i + 1]; ++j) {
+            orow[j] = i;
+            K[j] = m.K[j];
+            tg[j] = m.target ? m.target[j] : 0.0;
+            sw[j] = (weighting == SABR_W_RELATIVE && m.target) ? 1.0 / m.target[j] : 1.0;
+        }
+    }
+    mo[m.n_mat] = m.offs[m.n_mat];
+    g.t_max = 0.0;
+    for (int i = 0; i < m.n_mat; ++i) g.t_max = std::max(g.t_max, m.T[i]);
+    g.n_mat = m.n_mat;
+    g.n_obs = m.offs[m.n_mat];
+    int rc;
+    if ((rc = upload(c, S_MSTEPS, ms, &g.msteps)) || (rc = upload(c, S_MOFFS, mo, &g.moffs)) ||
+        (rc = upload(c, S_OBSROW, orow, &g.obsrow)) || (rc = upload(c, S_K, K, &g.K)) ||
+        (rc = upload(c, S_DISC, disc, &g.disc)) || (rc = upload(c, S_TARGET, tg, &g.target)) ||
+        (rc = upload(c, S_SW, sw, &g.sw)))
+        return rc;
+    return SABR_OK;
+}
+
+void crn_geometry(int64_t n_chains, int64_t n_paths, McCrnDesc &d) {
+    const int64_t tiles = (n_chains + 63) / 64;
+    int64_t nb = std::max<int64_t>(1, 4096 / tiles);
+    int64_t ppb = (n_paths + nb - 1) / nb;
+    ppb = std::max<int64_t>(ppb, 16);
+    ppb = std::min<int64_t>(ppb, 256);
+    nb = (n_paths + ppb - 1) / ppb;
+    d.n_pblocks = (int32_t)nb;
+    d.paths_per_block = ppb;
+}
+
+// f (and model prices) of n_x parameter vectors Ydev (device, row stride np) by CRN paths.
+int mc_objective_device(sabr_ctx *c, const McGrid &g, int model, int n_par, int beta_free, double beta,
+                        double f0, const sabr_mc &mc, int64_t n_x, const double *Ydev, double *fdev,
+                        double *modeldev, bool want_f, bool dominant) {
+    McCrnDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.n_mat = g.n_mat;
+    d.n_obs = g.n_obs;
+    d.m_max = g.m_max;
+    d.n_chains = n_x;
+    d.n_paths = mc.n_paths;
+    d.np_stride = n_par;
+    d.beta_free = beta_free;
+    d.dt = 1.0 / (double)mc.steps_per_year;
+    d.f0 = f0;
+    d.beta = beta;
+    d.key0 = (uint32_t)(mc.seed & 0xffffffffu);
+    d.key1 = (uint32_t)(mc.seed >> 32);
+    d.model = model;
+    d.t_max = g.t_max;
+    crn_geometry(n_x, mc.n_paths, d);
+    const int64_t tiles = (n_x + 63) / 64;
+    void *part;
+    int rc;
+    if ((rc = get_buf(c, S_PART, sizeof(float) * (size_t)tiles * g.n_obs * d.n_pblocks * 64, &part))) return rc;
+    const void *fn = mc_crn_kernel_ptr(model);
+    const size_t smem = mc_crn_smem_bytes(g.n_obs);
+    if ((rc = set_smem(c, fn, smem))) return rc;
+    const int32_t *ms = g.msteps, *mo = g.moffs;
+    const double *K = g.K;
+    void *a1[] = {&d, &Ydev, &ms, &mo, &K, &part};
+    if ((rc = launch(c, dominant, "mc_crn_kernel", fn, dim3((unsigned)(tiles * d.n_pblocks)), dim3(64), a1, smem)))
+        return rc;
+    const int32_t *orow = g.obsrow;
+    const double *disc = g.disc, *tg = g.target, *sw = g.sw;
+    const double *tgp = want_f ? tg : nullptr;
+    int wf = want_f ? 1 : 0;
+    void *a2[] = {&d, &Ydev, &part, &orow, &disc, &tgp, &sw, &fdev, &modeldev, &wf};
+    return launch(c, false, "mc_crn_reduce", mc_crn_reduce_ptr(), dim3((unsigned)((n_x + 255) / 256)), dim3(256), a2, 0);
+}
+
+int run_mc_request(sabr_ctx *c, const sabr_request &q, sabr_result &out) {
+    const sabr_market &m = q.market;
+    const sabr_problem &p = q.problem;
+    const int NP = p.n_par;
+    if (p.beta_free) return fail(c, SABR_E_INVAL, "the Monte Carlo objective needs a fixed beta");
+    if (q.sa.n_chains > 1 << 20) return fail(c, SABR_E_INVAL, "too many chains");
+    McGrid g;
+    int rc;
+    if ((rc = upload_mc_grid(c, m, q.mc.steps_per_year, q.obj.weighting, g))) return rc;
+    McSaDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.model = p.model;
+    d.n_par = NP;
+    d.n_chains = q.sa.n_chains;
+    d.n_iters = q.sa.n_iters;
+    d.chain_len = q.sa.chain_len;
+    d.key0 = (uint32_t)(q.sa.seed & 0xffffffffu);
+    d.key1 = (uint32_t)(q.sa.seed >> 32);
+    d.T0 = q.sa.T0;
+    double tmax = 0;
+    for (int i = 0; i < m.n_mat; ++i) tmax = std::max(tmax, m.T[i]);
+    d.t_max = tmax;
+    for (int k = 0; k < NP; ++k) {
+        d.lb[k] = p.lb[k];
+        d.ub[k] = p.ub[k];
+        d.x0[k] = p.x0 ? p.x0[k] : 0.5 * (p.lb[k] + p.ub[k]);
+    }
+    if (p.model == SABR_DYN_II && !case2_ok_host(d.x0, tmax))
+        return fail(c, SABR_E_INFEASIBLE, "case II start point violates the constraints");
+    const int n_levels = (q.sa.n_iters + q.sa.chain_len - 1) / q.sa.chain_len;
+    std::vector<double> sg(n_levels), sh(n_levels);
+    const double cL = std::pow(q.sa.cooling, (double)q.sa.chain_len);
+    double gk = 1.0;
+    for (int k = 0; k < n_levels; ++k) {
+        sg[k] = gk;
+        sh[k] = std::fmax(q.sa.step0 * std::sqrt(gk), q.sa.step_min);
+        gk = gk * cL;
+    }
+    double *dsg, *dsh;
+    if ((rc = upload(c, S_SCHED_G, sg, &dsg)) || (rc = upload(c, S_SCHED_H, sh, &dsh))) return rc;
+    const size_t P = (size_t)q.sa.n_chains;
+    void *Y, *cx, *cf, *bx, *bf, *fy, *st;
+    if ((rc = get_buf(c, S_Y, sizeof(double) * P * NP, &Y)) || (rc = get_buf(c, S_CX, sizeof(double) * P * NP, &cx)) ||
+        (rc = get_buf(c, S_CF, sizeof(double) * P, &cf)) || (rc = get_buf(c, S_BX, sizeof(double) * P * NP, &bx)) ||
+        (rc = get_buf(c, S_BF, sizeof(double) * P, &bf)) || (rc = get_buf(c, S_FY, sizeof(double) * P, &fy)) ||
+        (rc = get_buf(c, S_MCSTATE, sizeof(McSaState), &st)))
+        return rc;
+    // f(x0)
+    if ((rc = copy_h2d(c, Y, d.x0, sizeof(double) * NP))) return rc;
+    if ((rc = mc_objective_device(c, g, p.model, NP, 0, p.beta, m.fwd[0], q.mc, 1, (const double *)Y,
+                                  (double *)fy, nullptr, true, false)))
+        return rc;
+    const void *step = mc_sa_step_ptr();
+    int t = -1;
+    void *sargs[] = {&d, &t, &dsg, &dsh, &fy, &Y, &st, &cx, &cf, &bx, &bf};
+    if ((rc = launch(c, false, "mc_sa_step", step, dim3(1), dim3(1024), sargs, 0))) return rc;
+    for (t = 0; t < q.sa.n_iters; ++t) {
+        if ((rc = mc_objective_device(c, g, p.model, NP, 0, p.beta, m.fwd[0], q.mc, (int64_t)P, (const double *)Y,
+                                      (double *)fy, nullptr, true, true)))
+            return rc;
+        if ((rc = launch(c, false, "mc_sa_step", step, dim3(1), dim3(1024), sargs, 0))) return rc;
+    }
+    void *fargs[] = {&d, &bx, &bf, &st};
+    if ((rc = launch(c, false, "mc_sa_final", mc_sa_final_ptr(), dim3(1), dim3(64), fargs, 0))) return rc;
+    McSaState hs;
+    HIPCHK(c, hipMemcpyAsync(&hs, st, sizeof hs, hipMemcpyDeviceToHost, c->stream));
+    if ((rc = sync_and_account(c))) return rc;
+    std::memset(&out, 0, sizeof out);
+    for (int k = 0; k < NP; ++k) out.x[k] = hs.best_x[k];
+    out.f = hs.best_f;
+    out.f_before_polish = hs.best_f;
+    out.n_accept = (int64_t)hs.n_accept;
+    out.n_evals = 1 + (int64_t)P * q.sa.n_iters;
+    out.status = SABR_OK;
+    return SABR_OK;
+}
+
+}  // namespace
+
+// =====================================================================================
+// C ABI
+// =====================================================================================
+extern "C" {
+
+int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx **out) {
+    if (!out) return SABR_E_INVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+        hipGetLastError();
+        return SABR_E_INVAL;
+    }
+    sabr_ctx *c = new (std::nothrow) sabr_ctx();
+    if (!c) return SABR_E_NOMEM;
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return SABR_E_DEVICE;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return SABR_E_DEVICE;
+    }
+    c->n_cu = prop.multiProcessorCount;
+    int smem = 0;
+    hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
+    c->max_smem = (size_t)smem;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return SABR_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return SABR_OK;
+}
+
+void sabr_ctx_destroy(sabr_ctx *c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    hipStreamSynchronize(c->stream);
+    for (auto &b : c->bufs)
+        if (b.p) hipFree(b.p);
+    for (auto &e : c->pool) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    for (auto &e : c->pending) {
+        hipEventDestroy(e.a);
+        hipEventDestroy(e.b);
+    }
+    if (c->own_stream) hipStreamDestroy(c->stream);
+    if (c->stage) hipHostFree(c->stage);
+    delete c;
+}
+
+const char *sabr_ctx_last_error(const sabr_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int sabr_ctx_enable_timing(sabr_ctx *c, int enable) {
+    if (!c) return SABR_E_INVAL;
+    c->timing = enable != 0;
+    return SABR_OK;
+}
+
+int sabr_ctx_timing(sabr_ctx *c, int reset, double *kernel_ms, int64_t *launches, char *name, size_t name_len) {
+    if (!c) return SABR_E_INVAL;
+    if (kernel_ms) *kernel_ms = c->kernel_ms;
+    if (launches) *launches = c->launches;
+    if (name && name_len) {
+        std::strncpy(name, c->kernel_name.c_str(), name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    if (reset) {
+        c->kernel_ms = 0.0;
+        c->launches = 0;
+    }
+    return SABR_OK;
+}
+
+int sabr_calibrate(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_result *out) {
+    if (!c) return SABR_E_INVAL;
+    if (n_req < 1 || !reqs || !out) return fail(c, SABR_E_INVAL, "need n_req >= 1 and non-NULL arrays");
+    c->err.clear();
+    hipSetDevice(c->device);
+    int bad = 0;
+    std::string first_err;
+    for (int r = 0; r < n_req; ++r) {
+        const sabr_request &q = reqs[r];
+        std::memset(&out[r], 0, sizeof out[r]);
+        int rc;
+        const bool mc = q.obj.kind == SABR_OBJ_MC;
+        if ((rc = check_obj(c, &q.obj, q.problem.model)) || (rc = check_problem(c, &q.problem, true)) ||
+            (rc = check_market(c, &q.market, true, mc, q.obj.weighting)) || (rc = check_sa(c, &q.sa)) ||
+            (mc && (rc = check_mc(c, &q.mc)))) {
+            out[r].status = rc;
+            if (!bad) first_err = c->err;
+            ++bad;
+            continue;
+        }
+        if (q.problem.model == SABR_DYN_II && !mc) {
+            double x0[kMaxPar], tmax = 0;
+            for (int k = 0; k < q.problem.n_par; ++k)
+                x0[k] = q.problem.x0 ? q.problem.x0[k] : 0.5 * (q.problem.lb[k] + q.problem.ub[k]);
+            for (int i = 0; i < q.market.n_mat; ++i) tmax = std::max(tmax, q.market.T[i]);
+            if (!case2_ok_host(x0, tmax)) {
+                out[r].status = SABR_E_INFEASIBLE;
+                if (!bad) first_err = "case II start point violates the constraints";
+                ++bad;
+            }
+        }
+    }
+    if (bad) {
+        c->err = first_err;
+        return SABR_E_INVAL;
+    }
+    // group formula requests by kernel variant
+    std::vector<Group> groups;
+    for (int r = 0; r < n_req; ++r) {
+        const sabr_request &q = reqs[r];
+        if (q.obj.kind != SABR_OBJ_FORMULA) continue;
+        const int formula = q.problem.model == SABR_STATIC ? q.obj.formula : F_HAGAN;
+        const int fp32 = q.obj.precision == SABR_FP32;
+        const int bfree = q.problem.beta_free ? 1 : 0;
+        Group *gp = nullptr;
+        for (auto &g : groups)
+            if (g.model == q.problem.model && g.formula == formula && g.fp32 == fp32 && g.bfree == bfree) gp = &g;
+        if (!gp) {
+            groups.push_back(Group{q.problem.model, formula, fp32, bfree, {}});
+            gp = &groups.back();
+        }
+        gp->reqs.push_back(r);
+    }
+    for (auto &g : groups) {
+        int rc = run_formula_group(c, reqs, g, out);
+        if (rc) {
+            for (int r : g.reqs) out[r].status = rc;
+            return rc;
+        }
+    }
+    for (int r = 0; r < n_req; ++r) {
+        if (reqs[r].obj.kind != SABR_OBJ_MC) continue;
+        int rc = run_mc_request(c, reqs[r], out[r]);
+        if (rc) {
+            out[r].status = rc;
+            return rc;
+        }
+    }
+    return SABR_OK;
+}
+
+int sabr_objective_batch(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem,
+                         const sabr_objspec *obj, const sabr_mc *mc, int64_t n_x, const double *X, double *f,
+                         double *model) {
+    if (!c) return SABR_E_INVAL;
+    c->err.clear();
+    hipSetDevice(c->device);
+    int rc;
+    if ((rc = check_obj(c, obj, problem ? problem->model : 0))) return rc;
+    const bool is_mc = obj->kind == SABR_OBJ_MC;
+    if ((rc = check_problem(c, problem, false))) return rc;
+    if ((rc = check_market(c, market, false, is_mc, obj->weighting))) return rc;
+    if (is_mc && (rc = check_mc(c, mc))) return rc;
+    if (n_x < 0) return fail(c, SABR_E_INVAL, "n_x must be >= 0");
+    if (n_x == 0) return SABR_OK;
+    if (!X) return fail(c, SABR_E_INVAL, "X is NULL");
+    const bool want_f = market->target != nullptr;
+    if (!want_f && !model) return fail(c, SABR_E_INVAL, "no target and no model output: nothing to compute");
+    if (want_f && !f) return fail(c, SABR_E_INVAL, "f is NULL");
+    const int NP = problem->n_par;
+    const int n_obs = market->offs[market->n_mat];
+    const bool xd = is_device_ptr(X), fd = is_device_ptr(f), md = is_device_ptr(model);
+    const double *Xdev = X;
+    double *fdev = f, *mdev = model;
+    void *p;
+    if (!xd) {
+        if ((rc = get_buf(c, S_X, sizeof(double) * (size_t)n_x * NP, &p))) return rc;
+        if ((rc = copy_h2d(c, p, X, sizeof(double) * (size_t)n_x * NP))) return rc;
+        Xdev = (const double *)p;
+    }
+    if (want_f && !fd) {
+        if ((rc = get_buf(c, S_F, sizeof(double) * (size_t)n_x, &p))) return rc;
+        fdev = (double *)p;
+    }
+    if (model && !md) {
+        if ((rc = get_buf(c, S_MODEL, sizeof(double) * (size_t)n_x * n_obs, &p))) return rc;
+        mdev = (double *)p;
+    }
+    if (!is_mc) {
+        Packed pk;
+        int pt_off, mat_off;
+        pack_grid(pk, *market, *problem, *obj, pt_off, mat_off);
+        DevGrid g;
+        if ((rc = upload_grids(c, pk, g))) return rc;
+        ReqDesc d;
+        fill_desc(d, *market, *problem, *obj, pt_off, mat_off);
+        std::vector<ReqDesc> dv(1, d);
+        ReqDesc *dreq;
+        if ((rc = upload(c, S_REQ, dv, &dreq))) return rc;
+        const bool fp32 = obj->precision == SABR_FP32;
+        const int formula = problem->model == SABR_STATIC ? obj->formula : F_HAGAN;
+        const void *fn = objective_kernel_ptr(problem->model, formula, fp32, problem->beta_free != 0);
+        if (!fn) return fail(c, SABR_E_INVAL, "no objective kernel for this model/formula");
+        const size_t smem = grid_smem_bytes(fp32, d.n_pts, d.n_mat);
+        if ((rc = set_smem(c, fn, smem))) return rc;
+        const int64_t blocks = std::min<int64_t>((n_x + 255) / 256, 65535);
+        PointsD P = g.P;
+        MatsD Mt = g.Mt;
+        int wf = want_f ? 1 : 0;
+        void *args[] = {&dreq, &P, &Mt, &Xdev, &n_x, &fdev, &mdev, &wf};
+        if ((rc = launch(c, true, "objective_kernel", fn, dim3((unsigned)blocks), dim3(256), args, smem))) return rc;
+    } else {
+        if (problem->beta_free) return fail(c, SABR_E_INVAL, "the Monte Carlo objective needs a fixed beta");
+        McGrid g;
+        if ((rc = upload_mc_grid(c, *market, mc->steps_per_year, obj->weighting, g))) return rc;
+        if ((rc = mc_objective_device(c, g, problem->model, NP, 0, problem->beta, market->fwd[0], *mc, n_x, Xdev,
+                                      fdev, mdev, want_f, true)))
+            return rc;
+    }
+    if (want_f && !fd) HIPCHK(c, hipMemcpyAsync(f, fdev, sizeof(double) * (size_t)n_x, hipMemcpyDeviceToHost, c->stream));
+    if (model && !md)
+        HIPCHK(c, hipMemcpyAsync(model, mdev, sizeof(double) * (size_t)n_x * n_obs, hipMemcpyDeviceToHost, c->stream));
+    return sync_and_account(c);
+}
+
+int sabr_mc_price(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem, const sabr_mc *mc,
+                  int32_t precision, double *price, double *std_err) {
+    if (!c) return SABR_E_INVAL;
+    c->err.clear();
+    hipSetDevice(c->device);
+    int rc;
+    if ((rc = check_problem(c, problem, false))) return rc;
+    if (!problem->x0) return fail(c, SABR_E_INVAL, "problem->x0 (the parameters) is NULL");
+    if ((rc = check_market(c, market, false, true, SABR_W_ABSOLUTE))) return rc;
+    if ((rc = check_mc(c, mc))) return rc;
+    if (precision != SABR_FP32 && precision != SABR_FP64) return fail(c, SABR_E_INVAL, "bad precision");
+    if (!price) return fail(c, SABR_E_INVAL, "price is NULL");
+    McGrid g;
+    if ((rc = upload_mc_grid(c, *market, mc->steps_per_year, SABR_W_ABSOLUTE, g))) return rc;
+    McDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.model = problem->model;
+    d.n_mat = g.n_mat;
+    d.n_obs = g.n_obs;
+    d.m_max = g.m_max;
+    d.n_paths = mc->n_paths;
+    d.dt = 1.0 / (double)mc->steps_per_year;
+    d.f0 = market->fwd[0];
+    const int NP = problem->n_par;
+    d.beta = problem->beta_free ? problem->x0[NP - 1] : problem->beta;
+    for (int k = 0; k < base_npar(problem->model); ++k) d.x[k] = problem->x0[k];
+    d.key0 = (uint32_t)(mc->seed & 0xffffffffu);
+    d.key1 = (uint32_t)(mc->seed >> 32);
+    const bool fp32 = precision == SABR_FP32;
+    const int64_t tiles = (mc->n_paths + 255) / 256;
+    const int n_blocks = (int)std::min<int64_t>(tiles, 2048);
+    void *ps, *pq, *pr, *se;
+    if ((rc = get_buf(c, S_PART, sizeof(double) * (size_t)n_blocks * g.n_obs, &ps)) ||
+        (rc = get_buf(c, S_PARTQ, sizeof(double) * (size_t)n_blocks * g.n_obs, &pq)) ||
+        (rc = get_buf(c, S_PRICE, sizeof(double) * g.n_obs, &pr)) || (rc = get_buf(c, S_SE, sizeof(double) * g.n_obs, &se)))
+        return rc;
+    const void *fn = mc_price_kernel_ptr(fp32);
+    const size_t smem = mc_price_smem_bytes(fp32, g.m_max, g.n_obs);
+    if ((rc = set_smem(c, fn, smem))) return rc;
+    const int32_t *ms = g.msteps, *mo = g.moffs;
+    const double *K = g.K;
+    void *a1[] = {&d, &ms, &mo, &K, &ps, &pq};
+    if ((rc = launch(c, true, "mc_price_kernel", fn, dim3(n_blocks), dim3(256), a1, smem))) return rc;
+    int n_obs = g.n_obs;
+    int64_t np = mc->n_paths;
+    const int32_t *orow = g.obsrow;
+    const double *disc = g.disc;
+    int nblk = n_blocks;
+    void *a2[] = {&n_obs, &nblk, &np, &ps, &pq, &orow, &disc, &pr, &se};
+    if ((rc = launch(c, false, "mc_price_finalize", mc_price_finalize_ptr(), dim3((n_obs + 255) / 256), dim3(256), a2, 0)))
+        return rc;
+    HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
+    if (std_err) HIPCHK(c, hipMemcpyAsync(std_err, se, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
+    return sync_and_account(c);
+}
+
+}  // extern "C"

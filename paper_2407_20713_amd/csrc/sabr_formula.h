@@ -1,0 +1,193 @@
+// sabr_formula.h -- model implied volatilities and the market-fit objective
+// on one parameter vector, evaluated by one lane over a market grid staged in
+// LDS (Sections 2 and 3).
+#pragma once
+#include "sabr_dev.h"
+
+namespace sabr {
+
+// LDS point record (one per strike) and row record (one per maturity).
+template <typename R>
+struct alignas(16) Pt {
+    R P1, Z, Q1, Q2;      // beta fixed: leading factor, z factor, (Kf)^-(1-b)/2, (Kf)^-(1-b)
+    R lfk, lkf, T, pad;   // ln(f/K), ln(Kf), maturity
+    double target, sw;    // market value, sqrt(weight)
+};
+template <typename R>
+struct alignas(16) Row {
+    R T, lnf, F1, pad;    // maturity, ln f, f^(1-beta) (beta fixed)
+    int32_t p0, p1, q0, q1;
+};
+
+template <int MODEL>
+constexpr int base_npar() { return MODEL == MODEL_STATIC ? 3 : (MODEL == MODEL_DYN_I ? 5 : 9); }
+
+// Stage the points and rows of one request into LDS (all threads of the
+// block take part; the caller synchronises afterwards).
+template <typename R>
+__device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const MatsD &Mt,
+                                  Pt<R> *pts, Row<R> *rows) {
+    for (int j = threadIdx.x; j < rq.n_pts; j += blockDim.x) {
+        const int g = rq.pt_off + j;
+        Pt<R> p;
+        p.P1 = (R)P.P1[g];
+        p.Z = (R)P.Z[g];
+        p.Q1 = (R)P.Q1[g];
+        p.Q2 = (R)P.Q2[g];
+        p.lfk = (R)P.lfk[g];
+        p.lkf = (R)P.lkf[g];
+        p.T = (R)Mt.T[P.row[g]];
+        p.pad = (R)0;
+        p.target = P.target[g];
+        p.sw = P.sw[g];
+        pts[j] = p;
+    }
+    for (int i = threadIdx.x; i < rq.n_mat; i += blockDim.x) {
+        const int g = rq.mat_off + i;
+        Row<R> r;
+        r.T = (R)Mt.T[g];
+        r.lnf = (R)Mt.lnf[g];
+        r.F1 = (R)Mt.F1[g];
+        r.pad = (R)0;
+        r.p0 = Mt.offs[g] - rq.pt_off;
+        r.p1 = Mt.offs[g + 1] - rq.pt_off;
+        r.q0 = r.q1 = 0;
+        rows[i] = r;
+    }
+}
+
+// Row block of the expansion and of the dynamic formula:
+// sigma = inv_w (c0 + L (A1 + A2 L)) with L = ln(K/f), c0 = 1 + B T.
+template <typename R>
+struct Quad {
+    R inv_w, A1, A2, c0;
+};
+
+// eq. "vola_SABR": omega = f^(1-beta)/alpha.
+template <typename R>
+__device__ __forceinline__ Quad<R> expansion_block(R F1, R T, R al, R beta, R rho, R nu) {
+    const R omb = (R)1 - beta;
+    const R w = F1 / al;
+    const R rnw = rho * nu * w;
+    const R c3 = (R)2 - (R)3 * rho * rho;
+    Quad<R> q;
+    q.inv_w = al / F1;
+    q.A1 = (R)-0.5 * (omb - rnw);
+    q.A2 = (omb * omb + (R)3 * (omb - rnw) + c3 * nu * nu * w * w) * (R)(1.0 / 12.0);
+    const R B = omb * omb * (R)(1.0 / 24.0) * q.inv_w * q.inv_w + beta * rho * nu * (R)0.25 * q.inv_w
+              + c3 * (R)(1.0 / 24.0) * nu * nu;
+    q.c0 = fma(B, T, (R)1);
+    return q;
+}
+
+// eq. "vola_SABRd" from the four integrals {nu1^2, nu2^2, eta1, eta2^2}.
+template <typename R>
+__device__ __forceinline__ Quad<R> dynamic_block(R F1, R T, R al, R beta, R n1sq, R n2sq, R e1, R e2sq) {
+    const R omb = (R)1 - beta;
+    const R w = F1 / al;
+    Quad<R> q;
+    q.inv_w = al / F1;
+    q.A1 = (beta - (R)1) * (R)0.5 + e1 * w * (R)0.5;
+    q.A2 = omb * omb * (R)(1.0 / 12.0) + (omb - e1 * w) * (R)0.25
+         + ((R)4 * n1sq + (R)3 * (e2sq - (R)3 * e1 * e1)) * (R)(1.0 / 24.0) * w * w;
+    const R B = q.inv_w * q.inv_w * (omb * omb * (R)(1.0 / 24.0) + w * beta * e1 * (R)0.25
+                                     + ((R)2 * n2sq - (R)3 * e2sq) * (R)(1.0 / 24.0) * w * w);
+    q.c0 = fma(B, T, (R)1);
+    return q;
+}
+
+// Objective of one parameter vector y (double) over the staged grid:
+// sum over points of ((target - model) * sw)^2, accumulated in double.
+// A model vol that is not finite and positive, or an infeasible case II
+// vector, gives +inf.  WRITE stores the model vols to out[0..n_pts).
+template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE>
+__device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
+                            double beta_fixed, double t_max, double *out) {
+    constexpr int NP = base_npar<MODEL>() + (BFREE ? 1 : 0);
+    const double beta_d = BFREE ? y[NP - 1] : beta_fixed;
+    if (MODEL == MODEL_DYN_II && !case2_feasible(y, t_max)) return __builtin_inf();
+    const R al = (R)y[0], rh = (R)y[1], nu = (R)y[2];
+    const R beta = (R)beta_d, omb = (R)(1.0 - beta_d);
+    double acc = 0.0;
+    bool bad = false;
+
+    if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION) {
+        const R noa = nu / al;
+        const R c1a2 = omb * omb * (R)(1.0 / 24.0) * al * al;
+        const R c2rna = beta * (R)0.25 * rh * nu * al;
+        const R c3n2 = ((R)2 - (R)3 * rh * rh) * (R)(1.0 / 24.0) * nu * nu;
+        const R lr1 = M<R>::lg((R)1 - rh), lr2 = M<R>::lg((R)1 + rh);
+        const R d1 = omb * omb * (R)(1.0 / 24.0), d2 = d1 * d1 * (R)(576.0 / 1920.0);
+        for (int i = 0; i < n_mat; ++i) {
+            const Row<R> rw = rows[i];
+            R F1 = rw.F1;
+            if (BFREE && FORMULA == F_OBLOJ) F1 = M<R>::ex(omb * rw.lnf);
+            for (int j = rw.p0; j < rw.p1; ++j) {
+                const Pt<R> p = pts[j];
+                R P1, Z, Q1, Q2;
+                if constexpr (!BFREE) {
+                    P1 = p.P1; Z = p.Z; Q1 = p.Q1; Q2 = p.Q2;
+                } else {
+                    const R kf = M<R>::ex((R)0.5 * omb * p.lkf);
+                    Q1 = M<R>::rcp(kf);
+                    Q2 = Q1 * Q1;
+                    const R l2 = p.lfk * p.lfk;
+                    const R den = fma(l2, fma(d2, l2, d1), (R)1);
+                    if (FORMULA == F_HAGAN) {
+                        P1 = Q1 * M<R>::rcp(den);
+                        Z = kf * p.lfk;
+                    } else {
+                        const R u = omb * p.lfk;
+                        const R g = (u == (R)0) ? (R)1 : u / (-M<R>::em1(-u));
+                        P1 = g * M<R>::rcp(F1 * den);
+                        Z = F1 * p.lfk / g;
+                    }
+                }
+                const R z = noa * Z;
+                const R zx = M<R>::zx(z, rh, lr1, lr2);
+                const R corr = fma(fma(c1a2, Q2, fma(c2rna, Q1, c3n2)), p.T, (R)1);
+                const R sig = al * P1 * zx * corr;
+                bad |= !(sig > (R)0 && sig < (R)__builtin_inff());
+                const double e = (p.target - (double)sig) * p.sw;
+                acc = fma(e, e, acc);
+                if (WRITE) out[j] = (double)sig;
+            }
+        }
+    } else {
+        for (int i = 0; i < n_mat; ++i) {
+            const Row<R> rw = rows[i];
+            const R F1 = BFREE ? M<R>::ex(omb * rw.lnf) : rw.F1;
+            Quad<R> q;
+            if constexpr (MODEL == MODEL_STATIC) {
+                q = expansion_block<R>(F1, rw.T, al, beta, rh, nu);
+            } else if constexpr (MODEL == MODEL_DYN_I) {
+                const R a = (R)y[3], b = (R)y[4];
+                R n1, n2, e1, e2;
+                case1_normalised<R>((R)2 * b * rw.T, (a + b) * rw.T, n1, n2, e1, e2);
+                const R nr = nu * rh;
+                q = dynamic_block<R>(F1, rw.T, al, beta, nu * nu * n1, nu * nu * n2, nr * e1, nr * nr * e2);
+            } else {
+                FnII fp{y[1], y[2], y[3], y[4], y[5], y[6], y[7], y[8]};
+                const double Td = (double)rw.T;
+                const double kmax = fmax(fmax(y[3], y[4]), 1.0);
+                int np = (int)ceil(Td * kmax);
+                np = np < 1 ? 1 : (np > 64 ? 64 : np);
+                double ints[4];
+                case2_integrals(fp, Td, np, ints);
+                q = dynamic_block<R>(F1, rw.T, al, beta, (R)ints[0], (R)ints[1], (R)ints[2], (R)ints[3]);
+            }
+            for (int j = rw.p0; j < rw.p1; ++j) {
+                const Pt<R> p = pts[j];
+                const R L = -p.lfk;
+                const R sig = q.inv_w * fma(L, fma(q.A2, L, q.A1), q.c0);
+                bad |= !(sig > (R)0 && sig < (R)__builtin_inff());
+                const double e = (p.target - (double)sig) * p.sw;
+                acc = fma(e, e, acc);
+                if (WRITE) out[j] = (double)sig;
+            }
+        }
+    }
+    return bad ? __builtin_inf() : acc;
+}
+
+}  // namespace sabr
