@@ -11,7 +11,7 @@
  * Pinned by tests/test_oracle_pins.py against closed forms, limits, printed
  * values and brute force.  Parity unpinned: the case II asymptotic vols
  * (the paper prints none; only internal identities and quadrature
- * convergence cover them) and the compass-search polish end point.
+ * convergence cover them).
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no -ffast-math),
  * so that the annealing arithmetic is evaluated exactly as written.
@@ -688,35 +688,136 @@ int or_calibrate_levels(const or_sa_problem *pb, int32_t level_begin, int32_t le
     return 0;
 }
 
-/* Compass search from the annealing result (reading of the "best-so-far    */
-/* polish"): steps s_j = 1e-2 (ub_j - lb_j); each round evaluates the 2d    */
-/* neighbours x +/- s_j e_j (clamped to the box) in the order j = 0..d-1,   */
-/* + before -, and moves to the first that lowers f; a round without        */
-/* improvement halves every step.  Stops after 200 rounds or when the       */
-/* steps fall below 1e-10 (ub - lb).                                        */
-int or_polish(const or_sa_problem *pb, double *x, double *f, int64_t *n_evals)
+/* Residual vector of the formula objective: r_j = (D_mkt - D_model) * s_j  */
+/* with s_j = 1 (absolute) or 1/D_mkt (relative), so that f = sum r_j^2.     */
+/* Returns 0 if every model value is finite and positive.                    */
+static int residuals(const or_sa_problem *pb, const double *x, double *r)
 {
-    int d = pb->n_par;
-    double s[10], y[10], ybest[10];
-    for (int j = 0; j < d; ++j) s[j] = 1e-2 * (pb->ub[j] - pb->lb[j]);
-    for (int round = 0; round < 200; ++round) {
-        if (s[0] < 1e-10 * (pb->ub[0] - pb->lb[0])) break;
-        int found = 0;
-        double fbest = *f;
-        for (int j = 0; j < d; ++j) {
-            for (int sg = 0; sg < 2; ++sg) {
-                memcpy(y, x, sizeof(double) * (size_t)d);
-                y[j] = (sg == 0) ? x[j] + s[j] : x[j] - s[j];
-                if (y[j] > pb->ub[j]) y[j] = pb->ub[j];
-                if (y[j] < pb->lb[j]) y[j] = pb->lb[j];
-                double fy = eval_objective(pb, y);
-                ++*n_evals;
-                if (!found && fy < *f) { found = 1; fbest = fy; memcpy(ybest, y, sizeof(double) * (size_t)d); }
+    int n = pb->offs[pb->n_mat];
+    if (pb->model == OR_DYN_II) {
+        double tmax = 0.0;
+        for (int i = 0; i < pb->n_mat; ++i) tmax = fmax(tmax, pb->T[i]);
+        if (!or_case2_feasible(x, tmax)) return -1;
+    }
+    if (or_model_vols(pb->model, pb->formula, pb->beta, pb->beta_free, pb->n_par, x, pb->n_mat, pb->T,
+                      pb->fwd, pb->offs, pb->K, r)) return -1;
+    for (int j = 0; j < n; ++j) {
+        if (!isfinite(r[j]) || r[j] <= 0.0) return -1;
+        double e = pb->target[j] - r[j];
+        r[j] = (pb->weighting == OR_W_RELATIVE) ? e / pb->target[j] : e;
+    }
+    return 0;
+}
+
+static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* Solve (A + lambda D) d = -g by Cholesky, A symmetric d x d (row-major),   */
+/* D = diag(A) floored at 1e-12 of its mean.  Returns 0 on success.          */
+static int damped_solve(int d, const double *A, const double *g, double lambda, double *delta)
+{
+    double M[100], L[100], y[10], tr = 0.0;
+    for (int k = 0; k < d; ++k) tr += A[k * d + k];
+    double floor_ = 1e-12 * tr / d + 1e-300;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) M[a * d + b] = A[a * d + b];
+    for (int k = 0; k < d; ++k) M[k * d + k] += lambda * fmax(A[k * d + k], floor_);
+    for (int a = 0; a < d; ++a) {
+        for (int b = 0; b <= a; ++b) {
+            double s = M[a * d + b];
+            for (int k = 0; k < b; ++k) s -= L[a * d + k] * L[b * d + k];
+            if (a == b) {
+                if (!(s > 0.0)) return -1;
+                L[a * d + a] = sqrt(s);
+            } else {
+                L[a * d + b] = s / L[b * d + b];
             }
         }
-        if (found) { memcpy(x, ybest, sizeof(double) * (size_t)d); *f = fbest; }
-        else for (int j = 0; j < d; ++j) s[j] *= 0.5;
     }
+    for (int a = 0; a < d; ++a) {          /* L y = -g */
+        double s = -g[a];
+        for (int k = 0; k < a; ++k) s -= L[a * d + k] * y[k];
+        y[a] = s / L[a * d + a];
+    }
+    for (int a = d - 1; a >= 0; --a) {     /* L^T delta = y */
+        double s = y[a];
+        for (int k = a + 1; k < d; ++k) s -= L[k * d + a] * delta[k];
+        delta[a] = s / L[a * d + a];
+    }
+    return 0;
+}
+
+/* Levenberg-Marquardt polish of the annealing result (reading of the      */
+/* "best-so-far polish"), double precision, formula objective:             */
+/*   Jacobian of the residuals by central differences with steps            */
+/*   h_k = 6e-6 (ub_k - lb_k), clamped to the box;                           */
+/*   step: (J^T J + lambda diag(J^T J)) delta = -J^T r, y = clamp(x + delta);*/
+/*   accept if f(y) < f(x) (lambda /= 10, at least 1e-15), else lambda *= 10 */
+/*   and retry up to 12 times; lambda starts at 1e-3;                        */
+/*   at most 60 iterations; stops when f = 0, when no damping improves f,    */
+/*   or when an accepted step lowers f by less than 1e-15 f.                 */
+int or_polish(const or_sa_problem *pb, double *x, double *f, int64_t *n_evals)
+{
+    int d = pb->n_par, n = pb->offs[pb->n_mat];
+    double *r = malloc(sizeof(double) * (size_t)n), *rp = malloc(sizeof(double) * (size_t)n);
+    double *rm = malloc(sizeof(double) * (size_t)n), *J = malloc(sizeof(double) * (size_t)n * d);
+    if (!r || !rp || !rm || !J) { free(r); free(rp); free(rm); free(J); return -2; }
+    double lambda = 1e-3;
+    if (residuals(pb, x, r)) { free(r); free(rp); free(rm); free(J); return 0; }
+    double fx = 0.0;
+    for (int j = 0; j < n; ++j) fx += r[j] * r[j];
+    ++*n_evals;
+    for (int it = 0; it < 60 && fx > 0.0; ++it) {
+        for (int k = 0; k < d; ++k) {
+            double h = 6e-6 * (pb->ub[k] - pb->lb[k]);
+            double xp[10], xm[10];
+            memcpy(xp, x, sizeof(double) * (size_t)d);
+            memcpy(xm, x, sizeof(double) * (size_t)d);
+            xp[k] = clampd(x[k] + h, pb->lb[k], pb->ub[k]);
+            xm[k] = clampd(x[k] - h, pb->lb[k], pb->ub[k]);
+            double den = xp[k] - xm[k];
+            int bad = residuals(pb, xp, rp) | residuals(pb, xm, rm);
+            *n_evals += 2;
+            for (int j = 0; j < n; ++j) J[(size_t)j * d + k] = (den > 0.0 && !bad) ? (rp[j] - rm[j]) / den : 0.0;
+        }
+        double A[100], g[10];
+        for (int a = 0; a < d; ++a) {
+            g[a] = 0.0;
+            for (int j = 0; j < n; ++j) g[a] += J[(size_t)j * d + a] * r[j];
+            for (int b = 0; b < d; ++b) {
+                double s = 0.0;
+                for (int j = 0; j < n; ++j) s += J[(size_t)j * d + a] * J[(size_t)j * d + b];
+                A[a * d + b] = s;
+            }
+        }
+        int moved = 0;
+        double fnew = fx;
+        for (int tries = 0; tries < 12; ++tries) {
+            double delta[10], y[10];
+            if (damped_solve(d, A, g, lambda, delta) == 0) {
+                for (int k = 0; k < d; ++k) y[k] = clampd(x[k] + delta[k], pb->lb[k], pb->ub[k]);
+                ++*n_evals;
+                if (residuals(pb, y, rp) == 0) {
+                    double fy = 0.0;
+                    for (int j = 0; j < n; ++j) fy += rp[j] * rp[j];
+                    if (fy < fx) {
+                        memcpy(x, y, sizeof(double) * (size_t)d);
+                        memcpy(r, rp, sizeof(double) * (size_t)n);
+                        fnew = fy;
+                        lambda = fmax(lambda / 10.0, 1e-15);
+                        moved = 1;
+                        break;
+                    }
+                }
+            }
+            lambda *= 10.0;
+        }
+        if (!moved) break;
+        double gain = fx - fnew;
+        fx = fnew;
+        if (gain <= 1e-15 * fx) break;
+    }
+    *f = fx;
+    free(r); free(rp); free(rm); free(J);
     return 0;
 }
 
@@ -748,7 +849,7 @@ int or_calibrate(const or_sa_problem *pb, or_sa_result *res)
     memcpy(res->x, bx + (size_t)best * d, sizeof(double) * (size_t)d);
     res->f = bf[best];
     res->f_before_polish = bf[best];
-    if (pb->polish) or_polish(pb, res->x, &res->f, &ne);
+    if (pb->polish && pb->objective == OR_OBJ_FORMULA) or_polish(pb, res->x, &res->f, &ne);
     res->n_evals = ne;
     res->n_accept = na;
     res->status = 0;

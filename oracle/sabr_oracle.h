@@ -112,7 +112,7 @@ int or_calibrate(const or_sa_problem *pb, or_sa_result *res);
 int or_calibrate_levels(const or_sa_problem *pb, int32_t level_begin, int32_t level_end,
                         double *chain_x, double *chain_f, double *best_x, double *best_f,
                         int64_t *n_evals, int64_t *n_accept);
-/* compass-search polish (used after annealing) */
+/* Levenberg-Marquardt polish of a formula-objective result */
 int or_polish(const or_sa_problem *pb, double *x, double *f, int64_t *n_evals);
 
 #ifdef __cplusplus

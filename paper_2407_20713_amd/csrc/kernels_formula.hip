@@ -1,5 +1,5 @@
 // kernels_formula.hip -- grid normalisation, batch objective, persistent
-// synchronous annealing and compass polish (Sections 2, 3 and 5).
+// synchronous annealing and Levenberg-Marquardt polish (Sections 2, 3 and 5).
 #include "sabr_formula.h"
 #include "sabr_kernels.h"
 
@@ -162,38 +162,51 @@ __device__ void request_argmin(double f, int chain, bool active, const double *x
     }
     __syncthreads();
     if (rq.n_wg > 1) {
+        Cand *half = cands + rq.cand_off + (round & 1) * rq.n_wg;
         if (threadIdx.x == 0) {
-            Cand *half = cands + rq.cand_off + (round & 1) * rq.n_wg;
             Cand &c = half[wg_local];
             c.f = s.bf;
             c.chain = s.bid;
             for (int k = 0; k < NP; ++k) c.x[k] = s.bx[k];
-            __hip_atomic_fetch_add(&bar[req], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(&bar[req * kBarStride], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t want = (uint32_t)(round + 1) * (uint32_t)rq.n_wg;
             int spins = 0;
-            while (__hip_atomic_load(&bar[req], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < want) {
-                __builtin_amdgcn_s_sleep(2);
+            while (__hip_atomic_load(&bar[req * kBarStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                __builtin_amdgcn_s_sleep(1);
                 if (++spins > (1 << 24)) {
                     __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     break;
                 }
             }
-            int best = 0;
-            double bf = __hip_atomic_load(&half[0].f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            int bid = __hip_atomic_load(&half[0].chain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int w = 1; w < rq.n_wg; ++w) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        // the first wave reads every candidate at once and takes their argmin
+        if (threadIdx.x < 64) {
+            double cf = __builtin_inf();
+            int cid = 0x7fffffff, cw = 0;
+            for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
                 const double fw = __hip_atomic_load(&half[w].f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const int iw = __hip_atomic_load(&half[w].chain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (fw < bf || (fw == bf && iw < bid)) {
-                    bf = fw;
-                    bid = iw;
-                    best = w;
+                if (fw < cf || (fw == cf && iw < cid)) {
+                    cf = fw;
+                    cid = iw;
+                    cw = w;
                 }
             }
-            s.bf = bf;
-            s.bid = bid;
-            for (int k = 0; k < NP; ++k)
-                s.bx[k] = __hip_atomic_load(&half[best].x[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int key = cid;
+            double kf = cf;
+            wave_argmin(kf, key);
+            // the lane holding the winning chain id names its workgroup
+            const unsigned long long m = __ballot(cid == key && cf == kf);
+            const int src = __ffsll((long long)m) - 1;
+            const int bw = __shfl(cw, src, 64);
+            if (threadIdx.x < NP)
+                s.bx[threadIdx.x] = __hip_atomic_load(&half[bw].x[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) {
+                s.bf = kf;
+                s.bid = key;
+            }
         }
         __syncthreads();
     }
@@ -204,8 +217,8 @@ __device__ void request_argmin(double f, int chain, bool active, const double *x
 // one Markov chain; the workgroups of a request exchange their best state
 // at each level end; every chain restarts from the request's best.
 // ---------------------------------------------------------------------------
-template <int MODEL, int FORMULA, typename R, bool BFREE>
-__global__ void __launch_bounds__(kWG) sa_kernel(const ReqDesc *reqs, const int32_t *wg_req,
+template <int MODEL, int FORMULA, typename R, bool BFREE, int LPC>
+__global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const int32_t *wg_req,
                                                  PointsD P, MatsD Mt, const double *sched_g,
                                                  const double *sched_h, Cand *cands, uint32_t *bar,
                                                  ChainOut *best_out, unsigned long long *accepts,
@@ -227,17 +240,26 @@ __global__ void __launch_bounds__(kWG) sa_kernel(const ReqDesc *reqs, const int3
     }
     __syncthreads();
 
+    // LPC lanes share one chain: each takes every LPC-th strike and the
+    // partial sums are combined across the lane group; the chain state and
+    // its random words are the same on every lane of the group.
     const int wg_local = blockIdx.x - rq.wg_first;
-    const int chain = wg_local * kWG + threadIdx.x;
+    const int sub = threadIdx.x % LPC;
+    const int chain = wg_local * (kWG / LPC) + threadIdx.x / LPC;
     const bool active = chain < rq.n_chains;
     const int n_mat = rq.n_mat, L = rq.chain_len, n_iters = rq.n_iters;
     const double beta = rq.beta, tmax = rq.t_max;
     const uint32_t k0 = rq.key0, k1 = rq.key1;
+    auto f_of = [&](const double *v) {
+        double part = objective<MODEL, FORMULA, R, BFREE, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub);
+        if constexpr (LPC == 2) part = part + __shfl_xor(part, 1, 64);
+        return part;
+    };
 
     double x[NP], bx[NP], y[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) x[k] = bx[k] = rq.x0[k];
-    double fx = objective<MODEL, FORMULA, R, BFREE, false>(x, pts, rows, n_mat, beta, tmax, nullptr);
+    double fx = f_of(x);
     const double T0 = rq.T0 > 0.0 ? rq.T0 : ((fx > 0.0 && fx < __builtin_inf()) ? fx : 1.0);
     double fb = fx;
     unsigned long long nacc = 0;
@@ -261,7 +283,7 @@ __global__ void __launch_bounds__(kWG) sa_kernel(const ReqDesc *reqs, const int3
                 }
 #pragma unroll
                 for (int k = 0; k < NP; ++k) y[k] = propose_coord(x[k], u[k], h, s_lb[k], s_ub[k]);
-                const double fy = objective<MODEL, FORMULA, R, BFREE, false>(y, pts, rows, n_mat, beta, tmax, nullptr);
+                const double fy = f_of(y);
                 if (metropolis(fy, fx, u[NP], Tk)) {
 #pragma unroll
                     for (int k = 0; k < NP; ++k) x[k] = y[k];
@@ -284,7 +306,7 @@ __global__ void __launch_bounds__(kWG) sa_kernel(const ReqDesc *reqs, const int3
     // best-so-far over all chains of the request
     request_argmin<NP>(fb, chain, active, bx, am, rq, wg_local, round++, cands, bar, req, err);
     // accepted moves: workgroup sum, one integer atomic per workgroup
-    unsigned long long a = active ? nacc : 0ull;
+    unsigned long long a = (active && sub == 0) ? nacc : 0ull;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
     __shared__ unsigned long long s_acc[kWG / 64];
@@ -302,10 +324,82 @@ __global__ void __launch_bounds__(kWG) sa_kernel(const ReqDesc *reqs, const int3
 }
 
 // ---------------------------------------------------------------------------
-// Compass-search polish in double from the annealing result: lane l < 2 NP
-// evaluates x +/- s_j e_j (j = l/2, + for even l), the lowest improving lane
-// wins, no improvement halves every step.  One wave per request.
+// Levenberg-Marquardt polish in double from the annealing result (one wave
+// per request, lane = grid point).  Residuals r_j = (target - sigma_j) s_j;
+// Jacobian by central differences with h_k = 6e-6 (ub_k - lb_k) clamped to
+// the box; step (J^T J + lambda diag(J^T J)) d = -J^T r solved by Cholesky,
+// y = clamp(x + d); accept if f(y) < f(x) (lambda /= 10, floor 1e-15), else
+// lambda *= 10, up to 12 tries; at most 60 iterations; stop at f = 0, when no
+// damping helps, or when a step gains less than 1e-15 f.
 // ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum_bcast(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return __shfl(v, 0, 64);   // one association order for every lane
+}
+
+// Sum of squared residuals at v over the lane's points; `ok` false if any
+// model vol is not finite and positive (or v is an infeasible case II vector).
+template <int MODEL, int FORMULA, bool BFREE>
+__device__ double lm_f(const double *v, const Pt<double> *pts, const Row<double> *rows, const int32_t *prow,
+                       int n_pts, const ReqDesc &rq, bool &ok) {
+    ModelEval<MODEL, FORMULA, double, BFREE> ev;
+    bool good = ev.init(v, rq.beta, rq.t_max);
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n_pts && good; j += 64) {
+        ev.row(rows[prow[j]]);
+        const double sig = ev.point(pts[j]);
+        good &= vol_ok(sig);
+        const double e = fma(-sig, pts[j].sw, pts[j].tsw);
+        acc = fma(e, e, acc);
+    }
+    ok = __ballot(!good) == 0ull;
+    return wave_sum_bcast(acc);
+}
+
+template <int NP>
+__device__ __forceinline__ bool cholesky_solve(const double *A, const double *g, double lambda, double *d) {
+    double Mx[NP * NP], L[NP * NP], yv[NP];
+    double tr = 0.0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) tr += A[k * NP + k];
+    const double fl = 1e-12 * tr / NP + 1e-300;
+#pragma unroll
+    for (int a = 0; a < NP * NP; ++a) Mx[a] = A[a];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) Mx[k * NP + k] += lambda * fmax(A[k * NP + k], fl);
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            double s = Mx[a * NP + b];
+#pragma unroll
+            for (int k = 0; k < b; ++k) s -= L[a * NP + k] * L[b * NP + k];
+            if (a == b) {
+                if (!(s > 0.0)) return false;
+                L[a * NP + a] = sqrt(s);
+            } else {
+                L[a * NP + b] = s / L[b * NP + b];
+            }
+        }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        double s = -g[a];
+#pragma unroll
+        for (int k = 0; k < a; ++k) s -= L[a * NP + k] * yv[k];
+        yv[a] = s / L[a * NP + a];
+    }
+#pragma unroll
+    for (int a = NP - 1; a >= 0; --a) {
+        double s = yv[a];
+#pragma unroll
+        for (int k = a + 1; k < NP; ++k) s -= L[k * NP + a] * d[k];
+        d[a] = s / L[a * NP + a];
+    }
+    return true;
+}
+
 template <int MODEL, int FORMULA, bool BFREE>
 __global__ void __launch_bounds__(64) polish_kernel(const ReqDesc *reqs, const int32_t *req_ids,
                                                     PointsD P, MatsD Mt, ChainOut *best,
@@ -316,48 +410,100 @@ __global__ void __launch_bounds__(64) polish_kernel(const ReqDesc *reqs, const i
     const ReqDesc &rq = reqs[req];
     Pt<double> *pts = reinterpret_cast<Pt<double> *>(smem);
     Row<double> *rows = reinterpret_cast<Row<double> *>(smem + sizeof(Pt<double>) * rq.n_pts);
+    int32_t *prow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(rows) + sizeof(Row<double>) * rq.n_mat);
     stage_grid<double>(rq, P, Mt, pts, rows);
     __syncthreads();
-    const int lane = threadIdx.x;
-    double x[NP], s[NP], y[NP];
+    for (int i = 0; i < rq.n_mat; ++i)
+        for (int j = rows[i].p0 + threadIdx.x; j < rows[i].p1; j += 64) prow[j] = i;
+    __syncthreads();
+    const int n = rq.n_pts;
+    double x[NP], lb[NP], ub[NP], h[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) {
         x[k] = best[req].bx[k];
-        s[k] = 1e-2 * (rq.ub[k] - rq.lb[k]);
+        lb[k] = rq.lb[k];
+        ub[k] = rq.ub[k];
+        h[k] = 6e-6 * (ub[k] - lb[k]);
     }
-    double fx = objective<MODEL, FORMULA, double, BFREE, false>(x, pts, rows, rq.n_mat, rq.beta, rq.t_max, nullptr);
+    bool ok;
+    double fx = lm_f<MODEL, FORMULA, BFREE>(x, pts, rows, prow, n, rq, ok);
     unsigned long long ne = 1;
-    const int j = lane >> 1;
-    for (int round = 0; round < 200; ++round) {
-        if (s[0] < 1e-10 * (rq.ub[0] - rq.lb[0])) break;
-        double fy = __builtin_inf();
+    if (!ok) fx = __builtin_inf();
+    double lambda = 1e-3;
+    for (int it = 0; it < 60 && fx > 0.0 && fx < __builtin_inf(); ++it) {
+        double A[NP * NP], g[NP];
 #pragma unroll
-        for (int k = 0; k < NP; ++k) y[k] = x[k];
-        if (lane < 2 * NP) {
+        for (int a = 0; a < NP * NP; ++a) A[a] = 0.0;
 #pragma unroll
-            for (int k = 0; k < NP; ++k)
-                if (k == j) {
-                    double v = (lane & 1) ? x[k] - s[k] : x[k] + s[k];
-                    v = fmin(fmax(v, rq.lb[k]), rq.ub[k]);
-                    y[k] = v;
-                }
-            fy = objective<MODEL, FORMULA, double, BFREE, false>(y, pts, rows, rq.n_mat, rq.beta, rq.t_max, nullptr);
+        for (int a = 0; a < NP; ++a) g[a] = 0.0;
+        for (int j = threadIdx.x; j < n; j += 64) {
+            const Row<double> rw = rows[prow[j]];
+            const Pt<double> pj = pts[j];
+            ModelEval<MODEL, FORMULA, double, BFREE> ev;
+            ev.init(x, rq.beta, rq.t_max);
+            ev.row(rw);
+            const double r0 = fma(-ev.point(pj), pj.sw, pj.tsw);
+            double Jr[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                double xp[NP], xm[NP];
+#pragma unroll
+                for (int m = 0; m < NP; ++m) xp[m] = xm[m] = x[m];
+                xp[k] = fmin(fmax(x[k] + h[k], lb[k]), ub[k]);
+                xm[k] = fmin(fmax(x[k] - h[k], lb[k]), ub[k]);
+                const double den = xp[k] - xm[k];
+                ModelEval<MODEL, FORMULA, double, BFREE> ep, em;
+                const bool okp = ep.init(xp, rq.beta, rq.t_max), okm = em.init(xm, rq.beta, rq.t_max);
+                ep.row(rw);
+                em.row(rw);
+                const double sp = ep.point(pj), sm = em.point(pj);
+                const double rp = fma(-sp, pj.sw, pj.tsw), rm = fma(-sm, pj.sw, pj.tsw);
+                const bool good = okp && okm && den > 0.0 && vol_ok(sp) && vol_ok(sm);
+                Jr[k] = good ? (rp - rm) / den : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                g[a] = fma(Jr[a], r0, g[a]);
+#pragma unroll
+                for (int b = 0; b < NP; ++b) A[a * NP + b] = fma(Jr[a], Jr[b], A[a * NP + b]);
+            }
         }
         ne += 2 * NP;
-        const unsigned long long m = __ballot(lane < 2 * NP && fy < fx);
-        if (m) {
-            const int w = __ffsll((long long)m) - 1;
-            fx = __shfl(fy, w, 64);
 #pragma unroll
-            for (int k = 0; k < NP; ++k) x[k] = __shfl(y[k], w, 64);
-        } else {
+        for (int a = 0; a < NP * NP; ++a) A[a] = wave_sum_bcast(A[a]);
 #pragma unroll
-            for (int k = 0; k < NP; ++k) s[k] *= 0.5;
+        for (int a = 0; a < NP; ++a) g[a] = wave_sum_bcast(g[a]);
+        bool moved = false;
+        double fnew = fx;
+        for (int tries = 0; tries < 12; ++tries) {
+            double d[NP], y[NP];
+            if (cholesky_solve<NP>(A, g, lambda, d)) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) y[k] = fmin(fmax(x[k] + d[k], lb[k]), ub[k]);
+                bool oky;
+                const double fy = lm_f<MODEL, FORMULA, BFREE>(y, pts, rows, prow, n, rq, oky);
+                ++ne;
+                if (oky && fy < fx) {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) x[k] = y[k];
+                    fnew = fy;
+                    lambda = fmax(lambda / 10.0, 1e-15);
+                    moved = true;
+                    break;
+                }
+            }
+            lambda *= 10.0;
         }
+        if (!moved) break;
+        const double gain = fx - fnew;
+        fx = fnew;
+        if (gain <= 1e-15 * fx) break;
     }
-    if (lane == 0) {
-        best[req].bf = fx;
-        for (int k = 0; k < NP; ++k) best[req].bx[k] = x[k];
+    if (threadIdx.x == 0) {
+        if (fx <= best[req].bf || !(best[req].bf < __builtin_inf())) {
+            best[req].bf = fx;
+            for (int k = 0; k < NP; ++k) best[req].bx[k] = x[k];
+        }
         evals[req] = ne;
     }
 }
@@ -397,19 +543,31 @@ const void *objective_kernel_ptr(int model, int formula, bool fp32, bool bfree) 
     return v < 0 ? nullptr : (fp32 ? tab32[v] : tab64[v]);
 }
 
-const void *sa_kernel_ptr(int model, int formula, bool fp32, bool bfree) {
+const void *sa_kernel_ptr(int model, int formula, bool fp32, bool bfree, int lpc) {
     static const void *tab32[] = {
-#define SABR_P(MD, FM, BF) (const void *)sa_kernel<MD, FM, float, BF>,
+#define SABR_P(MD, FM, BF) (const void *)sa_kernel<MD, FM, float, BF, 1>,
         SABR_FORMULA_VARIANTS(SABR_P)
 #undef SABR_P
     };
     static const void *tab64[] = {
-#define SABR_P(MD, FM, BF) (const void *)sa_kernel<MD, FM, double, BF>,
+#define SABR_P(MD, FM, BF) (const void *)sa_kernel<MD, FM, double, BF, 1>,
+        SABR_FORMULA_VARIANTS(SABR_P)
+#undef SABR_P
+    };
+    static const void *tab32x2[] = {
+#define SABR_P(MD, FM, BF) (const void *)sa_kernel<MD, FM, float, BF, 2>,
+        SABR_FORMULA_VARIANTS(SABR_P)
+#undef SABR_P
+    };
+    static const void *tab64x2[] = {
+#define SABR_P(MD, FM, BF) (const void *)sa_kernel<MD, FM, double, BF, 2>,
         SABR_FORMULA_VARIANTS(SABR_P)
 #undef SABR_P
     };
     const int v = variant_index(model, formula, bfree);
-    return v < 0 ? nullptr : (fp32 ? tab32[v] : tab64[v]);
+    if (v < 0) return nullptr;
+    if (lpc == 2) return fp32 ? tab32x2[v] : tab64x2[v];
+    return fp32 ? tab32[v] : tab64[v];
 }
 
 const void *polish_kernel_ptr(int model, int formula, bool bfree) {

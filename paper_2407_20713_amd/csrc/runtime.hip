@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -47,6 +48,7 @@ struct sabr_ctx {
     std::string kernel_name;
     std::vector<EventPair> pending;
     std::vector<EventPair> pool;
+    int force_lpc = 0;   // SABR_LANES_PER_CHAIN overrides the choice (1 or 2)
     // pinned staging for host-to-device copies: valid until the next sync
     unsigned char *stage = nullptr;
     size_t stage_bytes = 0, stage_used = 0;
@@ -423,12 +425,23 @@ bool is_device_ptr(const void *p) {
 
 // --- formula calibration ------------------------------------------------------------
 struct Group {
-    int model, formula, fp32, bfree;
+    int model, formula, fp32, bfree, lpc;
     std::vector<int> reqs;
 };
 
+// Lanes per chain, a property of the request alone (so that its result never
+// depends on the other requests of a batch): requests of 1024 chains or more
+// split each chain's strikes over two lanes, which doubles the waves of the
+// few-but-large requests that would otherwise leave SIMDs half idle.
+int lanes_per_chain(const sabr_ctx *c, const sabr_request &q) {
+    if (c->force_lpc) return c->force_lpc;
+    return q.sa.n_chains >= 1024 ? 2 : 1;
+}
+
 int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, sabr_result *out) {
     const int nr = (int)grp.reqs.size();
+    const int lpc = grp.lpc;
+    const int chains_per_wg = kWG / lpc;
     Packed pk;
     std::vector<ReqDesc> desc(nr);
     std::vector<double> sg, sh;
@@ -456,7 +469,7 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
             sh.push_back(std::fmax(q.sa.step0 * std::sqrt(g), q.sa.step_min));
             g = g * cL;
         }
-        d.n_wg = (q.sa.n_chains + kWG - 1) / kWG;
+        d.n_wg = (q.sa.n_chains + chains_per_wg - 1) / chains_per_wg;
         d.wg_first = (int)wg_req.size();
         for (int w = 0; w < d.n_wg; ++w) wg_req.push_back(r);
         d.cand_off = cand_slots;
@@ -473,13 +486,13 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
         return rc;
     void *cand, *bar, *best, *acc, *err, *evals;
     if ((rc = get_buf(c, S_CAND, sizeof(Cand) * std::max(cand_slots, 1), &cand)) ||
-        (rc = get_buf(c, S_BAR, sizeof(uint32_t) * nr, &bar)) ||
+        (rc = get_buf(c, S_BAR, sizeof(uint32_t) * kBarStride * nr, &bar)) ||
         (rc = get_buf(c, S_BEST, sizeof(ChainOut) * nr, &best)) ||
         (rc = get_buf(c, S_ACC, sizeof(unsigned long long) * nr, &acc)) ||
         (rc = get_buf(c, S_ERR, sizeof(int32_t), &err)) ||
         (rc = get_buf(c, S_EVALS, sizeof(unsigned long long) * nr, &evals)))
         return rc;
-    HIPCHK(c, hipMemsetAsync(bar, 0, sizeof(uint32_t) * nr, c->stream));
+    HIPCHK(c, hipMemsetAsync(bar, 0, sizeof(uint32_t) * kBarStride * nr, c->stream));
     HIPCHK(c, hipMemsetAsync(acc, 0, sizeof(unsigned long long) * nr, c->stream));
     HIPCHK(c, hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
     HIPCHK(c, hipMemsetAsync(evals, 0, sizeof(unsigned long long) * nr, c->stream));
@@ -488,7 +501,7 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
     size_t smem = 0;
     for (int r = 0; r < nr; ++r) smem = std::max(smem, grid_smem_bytes(fp32, desc[r].n_pts, desc[r].n_mat));
     smem += sa_smem_fixed_bytes();
-    const void *fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0);
+    const void *fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0, lpc);
     if (!fn) return fail(c, SABR_E_INVAL, "no kernel for model %d formula %d", grp.model, grp.formula);
     if ((rc = set_smem(c, fn, smem))) return rc;
     const int n_blocks = (int)wg_req.size();
@@ -517,7 +530,8 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
         int32_t *dpol;
         if ((rc = upload(c, S_POLREQ, pol, &dpol))) return rc;
         size_t psm = 0;
-        for (int r : pol) psm = std::max(psm, grid_smem_bytes(false, desc[r].n_pts, desc[r].n_mat));
+        for (int r : pol)
+            psm = std::max(psm, grid_smem_bytes(false, desc[r].n_pts, desc[r].n_mat) + sizeof(int32_t) * desc[r].n_pts);
         const void *pf = polish_kernel_ptr(grp.model, grp.formula, grp.bfree != 0);
         if ((rc = set_smem(c, pf, psm))) return rc;
         void *pargs[] = {&dreq, &dpol, &P, &Mt, &best, &evals};
@@ -748,6 +762,10 @@ int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx 
         return SABR_E_DEVICE;
     }
     c->n_cu = prop.multiProcessorCount;
+    if (const char *e = std::getenv("SABR_LANES_PER_CHAIN")) {
+        const int v = std::atoi(e);
+        c->force_lpc = (v == 1 || v == 2) ? v : 0;
+    }
     int smem = 0;
     hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device);
     c->max_smem = (size_t)smem;
@@ -850,11 +868,14 @@ int sabr_calibrate(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_re
         const int formula = q.problem.model == SABR_STATIC ? q.obj.formula : F_HAGAN;
         const int fp32 = q.obj.precision == SABR_FP32;
         const int bfree = q.problem.beta_free ? 1 : 0;
+        const int lpc = lanes_per_chain(c, q);
         Group *gp = nullptr;
         for (auto &g : groups)
-            if (g.model == q.problem.model && g.formula == formula && g.fp32 == fp32 && g.bfree == bfree) gp = &g;
+            if (g.model == q.problem.model && g.formula == formula && g.fp32 == fp32 && g.bfree == bfree &&
+                g.lpc == lpc)
+                gp = &g;
         if (!gp) {
-            groups.push_back(Group{q.problem.model, formula, fp32, bfree, {}});
+            groups.push_back(Group{q.problem.model, formula, fp32, bfree, lpc, {}});
             gp = &groups.back();
         }
         gp->reqs.push_back(r);

@@ -71,12 +71,13 @@ struct ChainOut {
     double bx[kMaxPar];
 };
 
-struct Cand {             // level-end candidate of one workgroup
+struct alignas(128) Cand {   // level-end candidate of one workgroup (own cache line)
     double f;
     int32_t chain;
     int32_t pad;
     double x[kMaxPar];
 };
+constexpr int kBarStride = 64;   // uint32 words between the barrier counters of two requests
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10, from its published definition (Salmon et al., SC'11).
@@ -114,42 +115,64 @@ __device__ __forceinline__ double unit_u24d(uint32_t w) {
 // ---------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ double x_over_z_series(double z, double rho) {
-    double pm = 1.0, p = rho;          // P_0, P_1
-    double zn = z;
-    double s = fma(0.5 * rho, z, 1.0);
+    // q_n = P_n(rho) z^n by the Legendre recurrence in the variables rho z and
+    // z^2: q_(n+1) = (2n+1)/(n+1) (rho z) q_n - n/(n+1) z^2 q_(n-1).
+    const double t = rho * z, u = z * z;
+    double qm = 1.0, q = t;
+    double s = fma(0.5, t, 1.0);
 #pragma unroll
     for (int n = 1; n < NT - 1; ++n) {
-        // P_{n+1} = ((2n+1) rho P_n - n P_{n-1}) / (n+1)
-        const double pn = fma((double)(2 * n + 1) / (double)(n + 1) * rho, p,
-                              -(double)n / (double)(n + 1) * pm);
-        zn *= z;
-        s = fma(pn * (1.0 / (double)(n + 2)), zn, s);
-        pm = p;
-        p = pn;
+        const double qn = fma((double)(2 * n + 1) / (double)(n + 1) * t, q, -(double)n / (double)(n + 1) * u * qm);
+        s = fma(1.0 / (double)(n + 2), qn, s);
+        qm = q;
+        q = qn;
     }
     return s;
 }
+
+// Coefficients c_n = P_n(rho) / (n + 1) of the same series, for evaluating it
+// at many z with one rho (Horner in z).
+template <int NT>
+struct XzSeries {
+    double c[NT];
+    __device__ __forceinline__ void init(double rho) {
+        double pm = 1.0, p = rho;
+        c[0] = 1.0;
+        c[1] = 0.5 * rho;
+#pragma unroll
+        for (int n = 1; n < NT - 1; ++n) {
+            const double pn = fma((double)(2 * n + 1) / (double)(n + 1) * rho, p, -(double)n / (double)(n + 1) * pm);
+            c[n + 1] = pn * (1.0 / (double)(n + 2));
+            pm = p;
+            p = pn;
+        }
+    }
+    __device__ __forceinline__ double eval(double z) const {
+        double s = c[NT - 1];
+#pragma unroll
+        for (int n = NT - 2; n >= 0; --n) s = fma(s, z, c[n]);
+        return s;
+    }
+};
 
 // z / x(z), float bulk.  With zr = z - rho and s = sqrt(1 - 2 rho z + z^2):
 // x = ln(s + zr) - ln(1 - rho) for zr >= 0, and, rationalising with
 // (s + zr)(s - zr) = 1 - rho^2, x = ln(1 + rho) - ln(s - zr) for zr < 0;
 // both are sign(zr) (ln(s + |zr|) - ln(1 -/+ rho)).  lr1 = ln(1 - rho),
 // lr2 = ln(1 + rho) are per-chain constants.
-__device__ __forceinline__ float z_over_x_f32(float z, float rho, float lr1, float lr2) {
-    if (z == 0.0f) return 1.0f;
-    if (fabsf(z) < (float)kZIsland) {
-        return (float)(1.0 / x_over_z_series<8>((double)z, (double)rho));
-    }
+__device__ __forceinline__ float x_log_f32(float z, float rho, float lr1, float lr2) {
     const float zr = z - rho;
     const float s = __builtin_amdgcn_sqrtf(fmaf(z, z - 2.0f * rho, 1.0f));
     const float lg = __builtin_amdgcn_logf(s + fabsf(zr)) * kLn2f;
     const float xl = lg - (zr >= 0.0f ? lr1 : lr2);
-    const float x = zr >= 0.0f ? xl : -xl;
-    return z * __builtin_amdgcn_rcpf(x);
+    return zr >= 0.0f ? xl : -xl;
+}
+__device__ __forceinline__ float z_over_x_f32(float z, float rho, float lr1, float lr2) {
+    if (fabsf(z) < (float)kZIsland) return (float)(1.0 / x_over_z_series<8>((double)z, (double)rho));
+    return z * __builtin_amdgcn_rcpf(x_log_f32(z, rho, lr1, lr2));
 }
 
 __device__ __forceinline__ double z_over_x_f64(double z, double rho, double lr1, double lr2) {
-    if (z == 0.0) return 1.0;
     if (fabs(z) < kZIsland) return 1.0 / x_over_z_series<15>(z, rho);
     const double zr = z - rho;
     const double s = sqrt(fma(z, z - 2.0 * rho, 1.0));

@@ -11,7 +11,7 @@ template <typename R>
 struct alignas(16) Pt {
     R P1, Z, Q1, Q2;      // beta fixed: leading factor, z factor, (Kf)^-(1-b)/2, (Kf)^-(1-b)
     R lfk, lkf, T, pad;   // ln(f/K), ln(Kf), maturity
-    double target, sw;    // market value, sqrt(weight)
+    double tsw, sw;       // market value times sqrt(weight), sqrt(weight)
 };
 template <typename R>
 struct alignas(16) Row {
@@ -38,8 +38,8 @@ __device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const Mat
         p.lkf = (R)P.lkf[g];
         p.T = (R)Mt.T[P.row[g]];
         p.pad = (R)0;
-        p.target = P.target[g];
         p.sw = P.sw[g];
+        p.tsw = P.target[g] * p.sw;
         pts[j] = p;
     }
     for (int i = threadIdx.x; i < rq.n_mat; i += blockDim.x) {
@@ -96,68 +96,50 @@ __device__ __forceinline__ Quad<R> dynamic_block(R F1, R T, R al, R beta, R n1sq
     return q;
 }
 
-// Objective of one parameter vector y (double) over the staged grid:
-// sum over points of ((target - model) * sw)^2, accumulated in double.
-// A model vol that is not finite and positive, or an infeasible case II
-// vector, gives +inf.  WRITE stores the model vols to out[0..n_pts).
-template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE>
-__device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
-                            double beta_fixed, double t_max, double *out) {
-    constexpr int NP = base_npar<MODEL>() + (BFREE ? 1 : 0);
-    const double beta_d = BFREE ? y[NP - 1] : beta_fixed;
-    if (MODEL == MODEL_DYN_II && !case2_feasible(y, t_max)) return __builtin_inf();
-    const R al = (R)y[0], rh = (R)y[1], nu = (R)y[2];
-    const R beta = (R)beta_d, omb = (R)(1.0 - beta_d);
-    double acc = 0.0;
-    bool bad = false;
+// Model implied vol of one parameter vector, split into the part that depends
+// on the vector alone (init), on the maturity row (row) and on the strike
+// (point), so that a lane can evaluate a whole grid (objective) or a single
+// point (polish).
+template <int MODEL, int FORMULA, typename R, bool BFREE>
+struct ModelEval {
+    R al, rh, nu, beta, omb;
+    R noa, c1a2, c2rna, c3n2, lr1, lr2, d1, d2;   // z-form static formulas
+    R F1;                                         // f^(1-beta) of the current row
+    Quad<R> q;                                    // expansion / dynamic row block
+    XzSeries<8> xs;                               // near-the-money x(z)/z (float bulk)
+    const double *y;
 
-    if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION) {
-        const R noa = nu / al;
-        const R c1a2 = omb * omb * (R)(1.0 / 24.0) * al * al;
-        const R c2rna = beta * (R)0.25 * rh * nu * al;
-        const R c3n2 = ((R)2 - (R)3 * rh * rh) * (R)(1.0 / 24.0) * nu * nu;
-        const R lr1 = M<R>::lg((R)1 - rh), lr2 = M<R>::lg((R)1 + rh);
-        const R d1 = omb * omb * (R)(1.0 / 24.0), d2 = d1 * d1 * (R)(576.0 / 1920.0);
-        for (int i = 0; i < n_mat; ++i) {
-            const Row<R> rw = rows[i];
-            R F1 = rw.F1;
-            if (BFREE && FORMULA == F_OBLOJ) F1 = M<R>::ex(omb * rw.lnf);
-            for (int j = rw.p0; j < rw.p1; ++j) {
-                const Pt<R> p = pts[j];
-                R P1, Z, Q1, Q2;
-                if constexpr (!BFREE) {
-                    P1 = p.P1; Z = p.Z; Q1 = p.Q1; Q2 = p.Q2;
-                } else {
-                    const R kf = M<R>::ex((R)0.5 * omb * p.lkf);
-                    Q1 = M<R>::rcp(kf);
-                    Q2 = Q1 * Q1;
-                    const R l2 = p.lfk * p.lfk;
-                    const R den = fma(l2, fma(d2, l2, d1), (R)1);
-                    if (FORMULA == F_HAGAN) {
-                        P1 = Q1 * M<R>::rcp(den);
-                        Z = kf * p.lfk;
-                    } else {
-                        const R u = omb * p.lfk;
-                        const R g = (u == (R)0) ? (R)1 : u / (-M<R>::em1(-u));
-                        P1 = g * M<R>::rcp(F1 * den);
-                        Z = F1 * p.lfk / g;
-                    }
-                }
-                const R z = noa * Z;
-                const R zx = M<R>::zx(z, rh, lr1, lr2);
-                const R corr = fma(fma(c1a2, Q2, fma(c2rna, Q1, c3n2)), p.T, (R)1);
-                const R sig = al * P1 * zx * corr;
-                bad |= !(sig > (R)0 && sig < (R)__builtin_inff());
-                const double e = (p.target - (double)sig) * p.sw;
-                acc = fma(e, e, acc);
-                if (WRITE) out[j] = (double)sig;
-            }
+    // Returns false for a case II vector outside rho(t) in [-1,1], nu(t) > 0.
+    __device__ __forceinline__ bool init(const double *y_, double beta_fixed, double t_max) {
+        constexpr int NP = base_npar<MODEL>() + (BFREE ? 1 : 0);
+        y = y_;
+        const double beta_d = BFREE ? y[NP - 1] : beta_fixed;
+        al = (R)y[0];
+        rh = (R)y[1];
+        nu = (R)y[2];
+        beta = (R)beta_d;
+        omb = (R)(1.0 - beta_d);
+        if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION) {
+            noa = nu / al;
+            c1a2 = omb * omb * (R)(1.0 / 24.0) * al * al;
+            c2rna = beta * (R)0.25 * rh * nu * al;
+            c3n2 = ((R)2 - (R)3 * rh * rh) * (R)(1.0 / 24.0) * nu * nu;
+            lr1 = M<R>::lg((R)1 - rh);
+            lr2 = M<R>::lg((R)1 + rh);
+            d1 = omb * omb * (R)(1.0 / 24.0);
+            d2 = d1 * d1 * (R)(576.0 / 1920.0);
+            if constexpr (sizeof(R) == 4) xs.init(y[1]);
         }
-    } else {
-        for (int i = 0; i < n_mat; ++i) {
-            const Row<R> rw = rows[i];
-            const R F1 = BFREE ? M<R>::ex(omb * rw.lnf) : rw.F1;
-            Quad<R> q;
+        if (MODEL == MODEL_DYN_II) return case2_feasible(y, t_max);
+        return true;
+    }
+
+    __device__ __forceinline__ void row(const Row<R> &rw) {
+        if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION) {
+            F1 = rw.F1;
+            if (BFREE && FORMULA == F_OBLOJ) F1 = M<R>::ex(omb * rw.lnf);
+        } else {
+            F1 = BFREE ? M<R>::ex(omb * rw.lnf) : rw.F1;
             if constexpr (MODEL == MODEL_STATIC) {
                 q = expansion_block<R>(F1, rw.T, al, beta, rh, nu);
             } else if constexpr (MODEL == MODEL_DYN_I) {
@@ -176,15 +158,114 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
                 case2_integrals(fp, Td, np, ints);
                 q = dynamic_block<R>(F1, rw.T, al, beta, (R)ints[0], (R)ints[1], (R)ints[2], (R)ints[3]);
             }
-            for (int j = rw.p0; j < rw.p1; ++j) {
-                const Pt<R> p = pts[j];
-                const R L = -p.lfk;
-                const R sig = q.inv_w * fma(L, fma(q.A2, L, q.A1), q.c0);
-                bad |= !(sig > (R)0 && sig < (R)__builtin_inff());
-                const double e = (p.target - (double)sig) * p.sw;
-                acc = fma(e, e, acc);
-                if (WRITE) out[j] = (double)sig;
+        }
+    }
+
+    __device__ __forceinline__ R point(const Pt<R> &p) const {
+        if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION) {
+            R P1, Z, Q1, Q2;
+            if constexpr (!BFREE) {
+                P1 = p.P1; Z = p.Z; Q1 = p.Q1; Q2 = p.Q2;
+            } else {
+                const R kf = M<R>::ex((R)0.5 * omb * p.lkf);
+                Q1 = M<R>::rcp(kf);
+                Q2 = Q1 * Q1;
+                const R l2 = p.lfk * p.lfk;
+                const R den = fma(l2, fma(d2, l2, d1), (R)1);
+                if (FORMULA == F_HAGAN) {
+                    P1 = Q1 * M<R>::rcp(den);
+                    Z = kf * p.lfk;
+                } else {
+                    const R u = omb * p.lfk;
+                    const R g = (u == (R)0) ? (R)1 : u / (-M<R>::em1(-u));
+                    P1 = g * M<R>::rcp(F1 * den);
+                    Z = F1 * p.lfk / g;
+                }
             }
+            const R z = noa * Z;
+            R zx;
+            if constexpr (sizeof(R) == 4) {
+                zx = (fabsf(z) < (float)kZIsland) ? __builtin_amdgcn_rcpf((float)xs.eval((double)z))
+                                                   : z * __builtin_amdgcn_rcpf(x_log_f32(z, rh, lr1, lr2));
+            } else {
+                zx = M<R>::zx(z, rh, lr1, lr2);
+            }
+            const R corr = fma(fma(c1a2, Q2, fma(c2rna, Q1, c3n2)), p.T, (R)1);
+            return al * P1 * zx * corr;
+        } else {
+            const R L = -p.lfk;
+            return q.inv_w * fma(L, fma(q.A2, L, q.A1), q.c0);
+        }
+    }
+};
+
+template <typename R>
+__device__ __forceinline__ bool vol_ok(R sig) { return sig > (R)0 && sig < (R)__builtin_inff(); }
+
+// Objective of one parameter vector y (double) over the staged grid:
+// sum over points of ((target - model) * sw)^2, accumulated in double.
+// A model vol that is not finite and positive, or an infeasible case II
+// vector, gives +inf.  WRITE stores the model vols to out[0..n_pts).
+// With LPC > 1 lanes per parameter vector, lane `sub` takes the points
+// p0 + sub, p0 + sub + LPC, ... of every row and returns its partial sum.
+template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE, int LPC = 1>
+__device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
+                            double beta_fixed, double t_max, double *out, int sub = 0) {
+    ModelEval<MODEL, FORMULA, R, BFREE> ev;
+    if (!ev.init(y, beta_fixed, t_max)) return __builtin_inf();
+    double acc = 0.0;
+    bool bad = false;
+    if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION && !BFREE && sizeof(R) == 4 && !WRITE) {
+        // float hot loop of the static z-form formulas: two points per step so
+        // that their dependency chains interleave, the next pair's LDS records
+        // requested before the current pair is computed, and one branch per
+        // pair into the double near-the-money series.
+        for (int i = 0; i < n_mat; ++i) {
+            const Row<R> rw = rows[i];
+            const float c1a2 = ev.c1a2, c2rna = ev.c2rna, c3n2 = ev.c3n2, noa = ev.noa, alf = ev.al;
+            int j = rw.p0 + sub;
+            if (j >= rw.p1) continue;
+            Pt<R> na = pts[j], nb = pts[min(j + LPC, rw.p1 - 1)];
+            for (; j + LPC < rw.p1; j += 2 * LPC) {
+                const Pt<R> pa = na, pb = nb;
+                na = pts[min(j + 2 * LPC, rw.p1 - 1)];
+                nb = pts[min(j + 3 * LPC, rw.p1 - 1)];
+                const float za = noa * pa.Z, zb = noa * pb.Z;
+                float zxa = za * __builtin_amdgcn_rcpf(x_log_f32(za, ev.rh, ev.lr1, ev.lr2));
+                float zxb = zb * __builtin_amdgcn_rcpf(x_log_f32(zb, ev.rh, ev.lr1, ev.lr2));
+                const bool ia = fabsf(za) < (float)kZIsland, ib = fabsf(zb) < (float)kZIsland;
+                if (__builtin_expect(ia || ib, 0)) {
+                    if (ia) zxa = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)za));
+                    if (ib) zxb = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)zb));
+                }
+                const float ca = fmaf(fmaf(c1a2, pa.Q2, fmaf(c2rna, pa.Q1, c3n2)), pa.T, 1.0f);
+                const float cb = fmaf(fmaf(c1a2, pb.Q2, fmaf(c2rna, pb.Q1, c3n2)), pb.T, 1.0f);
+                const float sa = alf * pa.P1 * zxa * ca, sb = alf * pb.P1 * zxb * cb;
+                bad |= !vol_ok(sa) | !vol_ok(sb);
+                const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
+                acc = fma(ea, ea, acc);
+                acc = fma(eb, eb, acc);
+            }
+            if (j < rw.p1) {
+                const Pt<R> p = na;
+                const float sig = ev.point(p);
+                bad |= !vol_ok(sig);
+                const double e = fma(-(double)sig, p.sw, p.tsw);
+                acc = fma(e, e, acc);
+            }
+        }
+        return bad ? __builtin_inf() : acc;
+    }
+    for (int i = 0; i < n_mat; ++i) {
+        const Row<R> rw = rows[i];
+        ev.row(rw);
+        for (int j = rw.p0 + sub; j < rw.p1; j += LPC) {
+            const Pt<R> p = pts[j];
+            const R sig = ev.point(p);
+            bad |= !vol_ok(sig);
+            const double e = fma(-(double)sig, p.sw, p.tsw);
+            acc = fma(e, e, acc);
+            if (WRITE) out[j] = (double)sig;
         }
     }
     return bad ? __builtin_inf() : acc;

@@ -286,7 +286,7 @@ def smile_request(S, oracle, x_true, noise_sd, prec, n_chains, n_iters, seed, po
     return req, m, lb, ub
 
 
-@pytest.mark.parametrize("n_chains", [64, 600])
+@pytest.mark.parametrize("n_chains", [64, 600, 1300])
 def test_sa_fp64_matches_oracle_trajectory(S, ctx, oracle, n_chains):
     """FP64 mode takes the oracle's annealing decisions: same accepted-move
     count and the same best point (600 chains span 3 workgroups, ragged)."""
@@ -319,11 +319,30 @@ def test_sa_single_smile_recovery_fp32_and_fp64(S, ctx, oracle):
     assert gp["f"] <= gp["f_before_polish"] * (1 + 1e-6) + 1e-12
 
 
+@pytest.mark.parametrize("noise_sd", [0.0, 2e-3])
+def test_polish_matches_oracle(S, ctx, oracle, noise_sd):
+    """FP64 annealing (the oracle's decisions) followed by the double-precision
+    Levenberg-Marquardt polish: GPU and oracle end at the same point."""
+    x_true = np.array([0.2, -0.3, 0.5])
+    req, m, lb, ub = smile_request(S, oracle, x_true, noise_sd, S.SABR_FP64, 64, 300, 17, polish=True,
+                                   noise_seed=9)
+    got = S.sabr_calibrate(ctx, [req])[0]
+    ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, 64, 300, 17, polish=True)
+    say("polish gpu", got["x"], got["f"], "oracle", ref["x"], ref["f"])
+    assert got["f_before_polish"] == pytest.approx(ref["f_before_polish"], rel=1e-12)
+    np.testing.assert_allclose(got["x"], ref["x"], atol=1e-8)
+    assert abs(got["f"] - ref["f"]) <= 1e-9 * ref["f"] + 1e-28
+    if noise_sd == 0.0:
+        np.testing.assert_allclose(got["x"], x_true, atol=1e-9)
+
+
 def test_sa_batch_equals_alone(S, ctx, oracle):
-    """A request's result does not depend on the other requests of the batch."""
+    """A request's result does not depend on the other requests of the batch
+    (sizes on both sides of the two-lanes-per-chain threshold)."""
     reqs = []
-    for k, xt in enumerate(([0.2, -0.3, 0.5], [0.4, 0.2, 1.1], [0.1, -0.7, 0.3])):
-        r, _, _, _ = smile_request(S, oracle, np.array(xt), 1e-4, S.SABR_FP32, 256 + 64 * k, 300, 100 + k)
+    for k, xt in enumerate(([0.2, -0.3, 0.5], [0.4, 0.2, 1.1], [0.1, -0.7, 0.3], [0.3, 0.1, 0.8])):
+        r, _, _, _ = smile_request(S, oracle, np.array(xt), 1e-4, S.SABR_FP32, (256, 320, 1100, 2048)[k], 300,
+                                   100 + k)
         reqs.append(r)
     together = S.sabr_calibrate(ctx, reqs)
     for r, t in zip(reqs, together):

@@ -397,9 +397,57 @@ def test_sa_recovers_noise_free_smile(oracle):
     r = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, 64, 1000, 0x5AB10001, cooling=0.99,
                          polish=True)
     assert np.max(np.abs(r["x"] - x_true)) < 1e-3
-    assert r["f"] < 1e-10
+    assert r["f"] < 1e-20
     assert r["f"] <= r["f_before_polish"]
     assert r["n_evals"] > 64 * 1000
+
+
+def _surface_fit(oracle, k):
+    """Fit k of the static surface workload with its seeded true parameters."""
+    fits = inputs.surface_fits()
+    gens, lb, ub = inputs.surface_true_params(len(fits))
+    g = fits[k]
+    m = oracle.Market(g.T, g.fwd, g.offs, g.K)
+    while True:
+        x = inputs.draw_params(gens[k], lb, ub)
+        v = oracle.model_vols(m, oracle.STATIC, x, g.meta["beta"])
+        if np.all(np.isfinite(v)) and np.all(v > 0):
+            break
+    m.target = v
+    return m, g.meta["beta"], x, lb, ub
+
+
+def _polish(oracle, m, beta, lb, ub, start):
+    import ctypes as C
+    pb, keep = oracle._problem(m, oracle.STATIC, lb, ub, beta, 1, 1, 1, polish=True)
+    xs = (C.c_double * 10)(*list(start))
+    f = C.c_double(oracle.objective_formula(m, oracle.STATIC, start, beta))
+    ne = C.c_int64(0)
+    oracle.lib().or_polish(C.byref(pb), xs, C.byref(f), C.byref(ne))
+    return np.array(xs[:3]), f.value
+
+
+@pytest.mark.parametrize("k,offset", [(1, (0.0, 0.0166, 0.0005)), (7, (1e-4, -3e-4, 2e-4)),
+                                      (20, (-2e-3, 5e-3, 1e-2))])
+def test_polish_recovers_zero_residual_truth(oracle, k, offset):
+    """On noise-free surfaces the polish converges to the true parameters,
+    including a fit with nu = 0.013 where rho hardly moves the smile."""
+    m, beta, x, lb, ub = _surface_fit(oracle, k)
+    xp, f = _polish(oracle, m, beta, lb, ub, x + np.array(offset))
+    assert np.max(np.abs(xp - x)) < 1e-9
+    assert f < 1e-25
+
+
+def test_polish_reaches_a_least_squares_minimum(oracle):
+    """With noisy targets the polished point is a local minimum: no point of
+    a dense cube around it (brute force) has a lower objective."""
+    m, g = _smile_market(oracle, np.array([0.2, -0.3, 0.5]), noise_sd=2e-3, seed=9)
+    lb, ub = inputs.box(inputs.STATIC)
+    xp, f = _polish(oracle, m, 0.7, lb, ub, np.array([0.21, -0.25, 0.55]))
+    best = np.inf
+    for d in np.array(np.meshgrid(*[np.linspace(-1e-4, 1e-4, 7)] * 3)).reshape(3, -1).T:
+        best = min(best, oracle.objective_formula(m, oracle.STATIC, xp + d, 0.7))
+    assert f <= best * (1 + 1e-12)
 
 
 def test_sa_one_free_parameter_matches_brute_force(oracle):
