@@ -109,8 +109,8 @@ typedef struct {
  * at T0 * c^(k * chain_len) with c = cooling in (0, 1]; proposals move every
  * coordinate by h (2u - 1)(ub - lb), h = max(step0 * sqrt(c^(k chain_len)),
  * step_min), mirrored once at the bound and clamped.  polish != 0 runs a
- * double-precision compass search from the best state (formula objective
- * only).  Random words: Philox4x32-10 keyed by seed, counter (chain,
+ * double-precision Levenberg-Marquardt descent from the best state (formula
+ * objective only).  Random words: Philox4x32-10 keyed by seed, counter (chain,
  * iteration, block, 1). */
 typedef struct {
     int32_t n_chains, n_iters, chain_len;
@@ -194,6 +194,57 @@ int sabr_objective_batch(sabr_ctx *ctx, const sabr_market *market, const sabr_pr
  * standard error (std_err may be NULL).  Host arrays. */
 int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem,
                   const sabr_mc *mc, int32_t precision, double *price, double *std_err);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of calibration requests (Section 5, Techniques
+ * I and II, run for many independent requests at once).
+ *
+ * A worker thread owns a device-resident table of max_slots slots.  A
+ * submitted request waits in a FIFO queue until a slot of its kind is free
+ * and its device footprint (grid, schedule, chain state, Monte Carlo
+ * partials) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each quantum is
+ * one replay of a captured HIP graph that normalises new grids, advances
+ * every formula slot by quantum_levels temperature levels and every Monte
+ * Carlo slot by one iteration, and copies the slot states back; requests
+ * admitted while others run join at the next quantum.  Slots 0..max_slots/8-1
+ * take Monte Carlo requests, the others formula requests.
+ *
+ * Supported requests: FP32 precision, fixed beta, and either the static
+ * Hagan formula (<= 256 chains), the dynamic case I formula (<= 512 chains)
+ * or the static Monte Carlo objective (<= 64 chains, <= 512 options);
+ * grids up to 1024 points and 32 maturities.  Others: SABR_E_INVAL (use
+ * sabr_calibrate).  A request's result depends only on the request (its
+ * random words are keyed by its seed and chain ids, its sums run in a fixed
+ * order): it is the same alone, in any mix and for any quantum length.
+ *
+ * Thread safety: submit, poll, cancel and stats may be called from any host
+ * thread.  The server uses the context only for its device; it owns its own
+ * stream and memory.
+ * ------------------------------------------------------------------------- */
+typedef struct sabr_server sabr_server;
+
+/* Errors: SABR_E_INVAL (max_slots outside [2, 4096], quantum_levels < 1),
+ * SABR_E_NOMEM, SABR_E_DEVICE (graph capture failed). */
+int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes, int32_t quantum_levels,
+                       sabr_server **out);
+/* Copies the request (the caller may free its arrays on return) and queues
+ * it; *ticket identifies its result.  Errors: SABR_E_INVAL (invalid or
+ * unsupported request), SABR_E_BUDGET (larger than the whole budget). */
+int sabr_server_submit(sabr_server *srv, const sabr_request *req, uint64_t *ticket);
+/* Returns up to max finished requests (tickets[], res[], and, if not NULL,
+ * latency_s[] = completion minus submission in seconds), waiting up to
+ * timeout_us for the first one.  res[i].status is SABR_OK or
+ * SABR_E_CANCELLED.  Returns SABR_E_TIMEOUT if nothing finished in time. */
+int sabr_server_poll(sabr_server *srv, int32_t max, int32_t timeout_us, uint64_t *tickets, sabr_result *res,
+                     double *latency_s, int32_t *n_done);
+/* Cancels a queued or running request (its result comes back cancelled). */
+int sabr_server_cancel(sabr_server *srv, uint64_t ticket);
+/* Counters since creation (any pointer may be NULL). */
+int sabr_server_stats(sabr_server *srv, int64_t *quanta, int64_t *admitted, int64_t *completed, int64_t *queued,
+                      int32_t *active, size_t *bytes_in_use, size_t *peak_bytes, int32_t *peak_active);
+/* Stops the worker, waits for the current quantum and frees everything;
+ * results not yet polled are dropped. */
+int sabr_server_destroy(sabr_server *srv);
 
 #ifdef __cplusplus
 }

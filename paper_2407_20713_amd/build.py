@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB_PATH = os.path.join(HERE, "libsabr_hip.so")
-SOURCES = ["kernels_formula.hip", "kernels_mc.hip", "runtime.hip"]
+SOURCES = ["kernels_formula.hip", "kernels_mc.hip", "kernels_server.hip", "runtime.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -2,6 +2,7 @@
 // synchronous annealing and Levenberg-Marquardt polish (Sections 2, 3 and 5).
 #include "sabr_formula.h"
 #include "sabr_kernels.h"
+#include "sabr_sa.h"
 
 namespace sabr {
 
@@ -17,31 +18,8 @@ __global__ void prepare_points_kernel(int n_pts, const double *K, const double *
                                       double *Q2, double *sw) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_pts) return;
-    const double k = K[j], f = fwd_of_pt[j], beta = beta_of_pt[j];
-    const double omb = 1.0 - beta;
-    const double l = log(f / k);
-    const double lk = log(k * f);
-    const double kf = exp(0.5 * omb * lk);
-    const double l2 = l * l;
-    const double den = 1.0 + omb * omb / 24.0 * l2 + omb * omb * omb * omb / 1920.0 * l2 * l2;
-    lfk[j] = l;
-    lkf[j] = lk;
-    Q1[j] = 1.0 / kf;
-    Q2[j] = 1.0 / (kf * kf);
-    if (formula_of_pt[j] == F_OBLOJ) {
-        // z = (nu/alpha) f^(1-b) l / g(u), leading factor alpha g(u) / f^(1-b),
-        // g(u) = u / (1 - e^-u), u = (1-b) l.
-        const double F1 = exp(omb * log(f));
-        const double u = omb * l;
-        const double g = (u == 0.0) ? 1.0 : u / (-expm1(-u));
-        P1[j] = g / (F1 * den);
-        Z[j] = F1 * l / g;
-    } else {
-        P1[j] = 1.0 / (kf * den);
-        Z[j] = kf * l;
-    }
-    const double t = target ? target[j] : 0.0;
-    sw[j] = (weighting_of_pt[j] == W_RELATIVE) ? 1.0 / t : 1.0;
+    normalise_point(K[j], fwd_of_pt[j], beta_of_pt[j], formula_of_pt[j], weighting_of_pt[j],
+                    target ? target[j] : 0.0, lfk[j], lkf[j], P1[j], Z[j], Q1[j], Q2[j], sw[j]);
 }
 
 __global__ void prepare_mats_kernel(int n_mat, const double *fwd, const double *beta_of_mat,
@@ -80,135 +58,6 @@ __global__ void __launch_bounds__(256) objective_kernel(const ReqDesc *rqp, Poin
         else
             v = objective<MODEL, FORMULA, R, BFREE, false>(y, pts, rows, n_mat, beta, tmax, nullptr);
         if (write_f) f[i] = v;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Annealing arithmetic in double, evaluated exactly as written (no
-// contraction), so that float-free runs take the same decisions as any other
-// exact implementation of the same reading.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ double propose_coord(double x, double u, double h, double lb, double ub) {
-#pragma clang fp contract(off)
-    double y = x + (h * (2.0 * u - 1.0)) * (ub - lb);
-    if (y > ub) y = ub - (y - ub);
-    if (y < lb) y = lb + (lb - y);
-    if (y > ub) y = ub;
-    if (y < lb) y = lb;
-    return y;
-}
-
-__device__ __forceinline__ bool metropolis(double fy, double fx, double u, double Tk) {
-#pragma clang fp contract(off)
-    const double delta = fy - fx;
-    return delta <= 0.0 || u < exp(-delta / Tk);
-}
-
-// Wave-level argmin of (f, id): smaller f, ties to the smaller id.
-__device__ __forceinline__ void wave_argmin(double &f, int &id) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double fo = __shfl_xor(f, off, 64);
-        const int io = __shfl_xor(id, off, 64);
-        if (fo < f || (fo == f && io < id)) {
-            f = fo;
-            id = io;
-        }
-    }
-}
-
-struct ArgminSmem {
-    double wf[kWG / 64];
-    int wid[kWG / 64];
-    double bf;
-    int bid;
-    int pad;
-    double bx[kMaxPar];
-};
-
-// Level-end argmin over every chain of the request (workgroups of one request
-// exchange candidates through device memory and a counter).  Afterwards every
-// thread sees the winner in s.bf / s.bx.  `round` counts exchanges; slots
-// alternate between two halves so that a fast workgroup can never overwrite
-// a slot another one has not read yet.
-template <int NP>
-__device__ void request_argmin(double f, int chain, bool active, const double *x, ArgminSmem &s,
-                               const ReqDesc &rq, int wg_local, int round, Cand *cands, uint32_t *bar,
-                               int req, int32_t *err) {
-    double wf = active ? f : __builtin_inf();
-    int wid = active ? chain : 0x7fffffff;
-    wave_argmin(wf, wid);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
-        s.wf[wave] = wf;
-        s.wid[wave] = wid;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double bf = s.wf[0];
-        int bid = s.wid[0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-            if (s.wf[w] < bf || (s.wf[w] == bf && s.wid[w] < bid)) {
-                bf = s.wf[w];
-                bid = s.wid[w];
-            }
-        s.bf = bf;
-        s.bid = bid;
-    }
-    __syncthreads();
-    if (active && chain == s.bid) {
-#pragma unroll
-        for (int k = 0; k < NP; ++k) s.bx[k] = x[k];
-    }
-    __syncthreads();
-    if (rq.n_wg > 1) {
-        Cand *half = cands + rq.cand_off + (round & 1) * rq.n_wg;
-        if (threadIdx.x == 0) {
-            Cand &c = half[wg_local];
-            c.f = s.bf;
-            c.chain = s.bid;
-            for (int k = 0; k < NP; ++k) c.x[k] = s.bx[k];
-            __hip_atomic_fetch_add(&bar[req * kBarStride], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t want = (uint32_t)(round + 1) * (uint32_t)rq.n_wg;
-            int spins = 0;
-            while (__hip_atomic_load(&bar[req * kBarStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1 << 24)) {
-                    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        __syncthreads();
-        // the first wave reads every candidate at once and takes their argmin
-        if (threadIdx.x < 64) {
-            double cf = __builtin_inf();
-            int cid = 0x7fffffff, cw = 0;
-            for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
-                const double fw = __hip_atomic_load(&half[w].f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int iw = __hip_atomic_load(&half[w].chain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (fw < cf || (fw == cf && iw < cid)) {
-                    cf = fw;
-                    cid = iw;
-                    cw = w;
-                }
-            }
-            int key = cid;
-            double kf = cf;
-            wave_argmin(kf, key);
-            // the lane holding the winning chain id names its workgroup
-            const unsigned long long m = __ballot(cid == key && cf == kf);
-            const int src = __ffsll((long long)m) - 1;
-            const int bw = __shfl(cw, src, 64);
-            if (threadIdx.x < NP)
-                s.bx[threadIdx.x] = __hip_atomic_load(&half[bw].x[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (threadIdx.x == 0) {
-                s.bf = kf;
-                s.bid = key;
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -323,83 +172,6 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
     }
 }
 
-// ---------------------------------------------------------------------------
-// Levenberg-Marquardt polish in double from the annealing result (one wave
-// per request, lane = grid point).  Residuals r_j = (target - sigma_j) s_j;
-// Jacobian by central differences with h_k = 6e-6 (ub_k - lb_k) clamped to
-// the box; step (J^T J + lambda diag(J^T J)) d = -J^T r solved by Cholesky,
-// y = clamp(x + d); accept if f(y) < f(x) (lambda /= 10, floor 1e-15), else
-// lambda *= 10, up to 12 tries; at most 60 iterations; stop at f = 0, when no
-// damping helps, or when a step gains less than 1e-15 f.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_sum_bcast(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return __shfl(v, 0, 64);   // one association order for every lane
-}
-
-// Sum of squared residuals at v over the lane's points; `ok` false if any
-// model vol is not finite and positive (or v is an infeasible case II vector).
-template <int MODEL, int FORMULA, bool BFREE>
-__device__ double lm_f(const double *v, const Pt<double> *pts, const Row<double> *rows, const int32_t *prow,
-                       int n_pts, const ReqDesc &rq, bool &ok) {
-    ModelEval<MODEL, FORMULA, double, BFREE> ev;
-    bool good = ev.init(v, rq.beta, rq.t_max);
-    double acc = 0.0;
-    for (int j = threadIdx.x; j < n_pts && good; j += 64) {
-        ev.row(rows[prow[j]]);
-        const double sig = ev.point(pts[j]);
-        good &= vol_ok(sig);
-        const double e = fma(-sig, pts[j].sw, pts[j].tsw);
-        acc = fma(e, e, acc);
-    }
-    ok = __ballot(!good) == 0ull;
-    return wave_sum_bcast(acc);
-}
-
-template <int NP>
-__device__ __forceinline__ bool cholesky_solve(const double *A, const double *g, double lambda, double *d) {
-    double Mx[NP * NP], L[NP * NP], yv[NP];
-    double tr = 0.0;
-#pragma unroll
-    for (int k = 0; k < NP; ++k) tr += A[k * NP + k];
-    const double fl = 1e-12 * tr / NP + 1e-300;
-#pragma unroll
-    for (int a = 0; a < NP * NP; ++a) Mx[a] = A[a];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) Mx[k * NP + k] += lambda * fmax(A[k * NP + k], fl);
-#pragma unroll
-    for (int a = 0; a < NP; ++a)
-#pragma unroll
-        for (int b = 0; b <= a; ++b) {
-            double s = Mx[a * NP + b];
-#pragma unroll
-            for (int k = 0; k < b; ++k) s -= L[a * NP + k] * L[b * NP + k];
-            if (a == b) {
-                if (!(s > 0.0)) return false;
-                L[a * NP + a] = sqrt(s);
-            } else {
-                L[a * NP + b] = s / L[b * NP + b];
-            }
-        }
-#pragma unroll
-    for (int a = 0; a < NP; ++a) {
-        double s = -g[a];
-#pragma unroll
-        for (int k = 0; k < a; ++k) s -= L[a * NP + k] * yv[k];
-        yv[a] = s / L[a * NP + a];
-    }
-#pragma unroll
-    for (int a = NP - 1; a >= 0; --a) {
-        double s = yv[a];
-#pragma unroll
-        for (int k = a + 1; k < NP; ++k) s -= L[k * NP + a] * d[k];
-        d[a] = s / L[a * NP + a];
-    }
-    return true;
-}
-
 template <int MODEL, int FORMULA, bool BFREE>
 __global__ void __launch_bounds__(64) polish_kernel(const ReqDesc *reqs, const int32_t *req_ids,
                                                     PointsD P, MatsD Mt, ChainOut *best,
@@ -416,89 +188,11 @@ __global__ void __launch_bounds__(64) polish_kernel(const ReqDesc *reqs, const i
     for (int i = 0; i < rq.n_mat; ++i)
         for (int j = rows[i].p0 + threadIdx.x; j < rows[i].p1; j += 64) prow[j] = i;
     __syncthreads();
-    const int n = rq.n_pts;
-    double x[NP], lb[NP], ub[NP], h[NP];
+    double x[NP];
 #pragma unroll
-    for (int k = 0; k < NP; ++k) {
-        x[k] = best[req].bx[k];
-        lb[k] = rq.lb[k];
-        ub[k] = rq.ub[k];
-        h[k] = 6e-6 * (ub[k] - lb[k]);
-    }
-    bool ok;
-    double fx = lm_f<MODEL, FORMULA, BFREE>(x, pts, rows, prow, n, rq, ok);
-    unsigned long long ne = 1;
-    if (!ok) fx = __builtin_inf();
-    double lambda = 1e-3;
-    for (int it = 0; it < 60 && fx > 0.0 && fx < __builtin_inf(); ++it) {
-        double A[NP * NP], g[NP];
-#pragma unroll
-        for (int a = 0; a < NP * NP; ++a) A[a] = 0.0;
-#pragma unroll
-        for (int a = 0; a < NP; ++a) g[a] = 0.0;
-        for (int j = threadIdx.x; j < n; j += 64) {
-            const Row<double> rw = rows[prow[j]];
-            const Pt<double> pj = pts[j];
-            ModelEval<MODEL, FORMULA, double, BFREE> ev;
-            ev.init(x, rq.beta, rq.t_max);
-            ev.row(rw);
-            const double r0 = fma(-ev.point(pj), pj.sw, pj.tsw);
-            double Jr[NP];
-#pragma unroll
-            for (int k = 0; k < NP; ++k) {
-                double xp[NP], xm[NP];
-#pragma unroll
-                for (int m = 0; m < NP; ++m) xp[m] = xm[m] = x[m];
-                xp[k] = fmin(fmax(x[k] + h[k], lb[k]), ub[k]);
-                xm[k] = fmin(fmax(x[k] - h[k], lb[k]), ub[k]);
-                const double den = xp[k] - xm[k];
-                ModelEval<MODEL, FORMULA, double, BFREE> ep, em;
-                const bool okp = ep.init(xp, rq.beta, rq.t_max), okm = em.init(xm, rq.beta, rq.t_max);
-                ep.row(rw);
-                em.row(rw);
-                const double sp = ep.point(pj), sm = em.point(pj);
-                const double rp = fma(-sp, pj.sw, pj.tsw), rm = fma(-sm, pj.sw, pj.tsw);
-                const bool good = okp && okm && den > 0.0 && vol_ok(sp) && vol_ok(sm);
-                Jr[k] = good ? (rp - rm) / den : 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < NP; ++a) {
-                g[a] = fma(Jr[a], r0, g[a]);
-#pragma unroll
-                for (int b = 0; b < NP; ++b) A[a * NP + b] = fma(Jr[a], Jr[b], A[a * NP + b]);
-            }
-        }
-        ne += 2 * NP;
-#pragma unroll
-        for (int a = 0; a < NP * NP; ++a) A[a] = wave_sum_bcast(A[a]);
-#pragma unroll
-        for (int a = 0; a < NP; ++a) g[a] = wave_sum_bcast(g[a]);
-        bool moved = false;
-        double fnew = fx;
-        for (int tries = 0; tries < 12; ++tries) {
-            double d[NP], y[NP];
-            if (cholesky_solve<NP>(A, g, lambda, d)) {
-#pragma unroll
-                for (int k = 0; k < NP; ++k) y[k] = fmin(fmax(x[k] + d[k], lb[k]), ub[k]);
-                bool oky;
-                const double fy = lm_f<MODEL, FORMULA, BFREE>(y, pts, rows, prow, n, rq, oky);
-                ++ne;
-                if (oky && fy < fx) {
-#pragma unroll
-                    for (int k = 0; k < NP; ++k) x[k] = y[k];
-                    fnew = fy;
-                    lambda = fmax(lambda / 10.0, 1e-15);
-                    moved = true;
-                    break;
-                }
-            }
-            lambda *= 10.0;
-        }
-        if (!moved) break;
-        const double gain = fx - fnew;
-        fx = fnew;
-        if (gain <= 1e-15 * fx) break;
-    }
+    for (int k = 0; k < NP; ++k) x[k] = best[req].bx[k];
+    unsigned long long ne = 0;
+    const double fx = lm_polish<MODEL, FORMULA, BFREE>(x, pts, rows, prow, rq, &ne);
     if (threadIdx.x == 0) {
         if (fx <= best[req].bf || !(best[req].bf < __builtin_inf())) {
             best[req].bf = fx;

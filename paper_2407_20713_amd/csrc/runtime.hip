@@ -56,16 +56,12 @@ struct sabr_ctx {
 
 namespace {
 
+}  // namespace
+namespace sabrhost {
 int fail(sabr_ctx *c, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
-int fail(sabr_ctx *c, int code, const char *fmt, ...) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    if (c) c->err = buf;
-    return code;
 }
+namespace {
+using namespace sabrhost;
 
 #define HIPCHK(ctx, expr)                                                                   \
     do {                                                                                    \
@@ -211,6 +207,19 @@ int set_smem(sabr_ctx *c, const void *fn, size_t smem) {
     return SABR_OK;
 }
 
+}  // namespace
+
+namespace sabrhost {
+int fail(sabr_ctx *c, int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+int device_of(const sabr_ctx *c) { return c->device; }
 int base_npar(int model) { return model == SABR_STATIC ? 3 : (model == SABR_DYN_I ? 5 : (model == SABR_DYN_II ? 9 : -1)); }
 
 int n_steps(double T, int spy) {
@@ -218,7 +227,7 @@ int n_steps(double T, int spy) {
     return m < 1 ? 1 : m;
 }
 
-bool finite(double v) { return std::isfinite(v); }
+static bool finite(double v) { return std::isfinite(v); }
 
 // --- validation ---------------------------------------------------------------
 int check_market(sabr_ctx *c, const sabr_market *m, bool need_target, bool mc, int weighting) {
@@ -299,6 +308,22 @@ int check_sa(sabr_ctx *c, const sabr_sa *s) {
     if (!(s->step0 > 0.0) || !(s->step_min >= 0.0)) return fail(c, SABR_E_INVAL, "step sizes invalid");
     return SABR_OK;
 }
+
+// Validation of one calibration request (shared by sabr_calibrate and the server).
+int check_request(sabr_ctx *c, const sabr_request &q) {
+    int rc;
+    const bool mc = q.obj.kind == SABR_OBJ_MC;
+    if ((rc = check_obj(c, &q.obj, q.problem.model)) || (rc = check_problem(c, &q.problem, true)) ||
+        (rc = check_market(c, &q.market, true, mc, q.obj.weighting)) || (rc = check_sa(c, &q.sa)) ||
+        (mc && (rc = check_mc(c, &q.mc))))
+        return rc;
+    return SABR_OK;
+}
+
+}  // namespace sabrhost
+
+namespace {
+using namespace sabrhost;
 
 bool case2_ok_host(const double *x, double tmax) {
     auto range = [&](double c0, double c1, double k, double d, double &lo, double &hi) {

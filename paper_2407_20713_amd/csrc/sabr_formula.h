@@ -22,6 +22,37 @@ struct alignas(16) Row {
 template <int MODEL>
 constexpr int base_npar() { return MODEL == MODEL_STATIC ? 3 : (MODEL == MODEL_DYN_I ? 5 : 9); }
 
+// Grid normalisation of one point (double): ln(f/K), ln(Kf) and, for a fixed
+// beta, the alpha-free factors of eqs. "haganf" / "sigma-SABR":
+// Hagan: P1 = 1 / ((Kf)^((1-b)/2) den), Z = (Kf)^((1-b)/2) ln(f/K);
+// Oblój: z = (nu/alpha) f^(1-b) l / g(u), leading factor alpha g(u) / f^(1-b),
+// g(u) = u / (1 - e^-u), u = (1-b) l; den = 1 + (1-b)^2 l^2/24 + (1-b)^4 l^4/1920.
+__device__ inline void normalise_point(double k, double f, double beta, int formula, int weighting, double t,
+                                       double &lfk, double &lkf, double &P1, double &Z, double &Q1, double &Q2,
+                                       double &sw) {
+    const double omb = 1.0 - beta;
+    const double l = log(f / k);
+    const double lk = log(k * f);
+    const double kf = exp(0.5 * omb * lk);
+    const double l2 = l * l;
+    const double den = 1.0 + omb * omb / 24.0 * l2 + omb * omb * omb * omb / 1920.0 * l2 * l2;
+    lfk = l;
+    lkf = lk;
+    Q1 = 1.0 / kf;
+    Q2 = 1.0 / (kf * kf);
+    if (formula == F_OBLOJ) {
+        const double F1 = exp(omb * log(f));
+        const double u = omb * l;
+        const double g = (u == 0.0) ? 1.0 : u / (-expm1(-u));
+        P1 = g / (F1 * den);
+        Z = F1 * l / g;
+    } else {
+        P1 = 1.0 / (kf * den);
+        Z = kf * l;
+    }
+    sw = (weighting == W_RELATIVE) ? 1.0 / t : 1.0;
+}
+
 // Stage the points and rows of one request into LDS (all threads of the
 // block take part; the caller synchronises afterwards).
 template <typename R>

@@ -1,0 +1,311 @@
+// sabr_sa.h -- device pieces of the synchronous annealing (Section 5) shared
+// by the batch kernel and the serving kernels: proposal and Metropolis test
+// in double without contraction, the level-end argmin with its
+// cross-workgroup exchange, and the Levenberg-Marquardt polish.
+#pragma once
+#include "sabr_formula.h"
+
+namespace sabr {
+
+// ---------------------------------------------------------------------------
+// Annealing arithmetic in double, evaluated exactly as written (no
+// contraction), so that float-free runs take the same decisions as any other
+// exact implementation of the same reading.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double propose_coord(double x, double u, double h, double lb, double ub) {
+#pragma clang fp contract(off)
+    double y = x + (h * (2.0 * u - 1.0)) * (ub - lb);
+    if (y > ub) y = ub - (y - ub);
+    if (y < lb) y = lb + (lb - y);
+    if (y > ub) y = ub;
+    if (y < lb) y = lb;
+    return y;
+}
+
+__device__ __forceinline__ bool metropolis(double fy, double fx, double u, double Tk) {
+#pragma clang fp contract(off)
+    const double delta = fy - fx;
+    return delta <= 0.0 || u < exp(-delta / Tk);
+}
+
+// Wave-level argmin of (f, id): smaller f, ties to the smaller id.
+__device__ __forceinline__ void wave_argmin(double &f, int &id) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double fo = __shfl_xor(f, off, 64);
+        const int io = __shfl_xor(id, off, 64);
+        if (fo < f || (fo == f && io < id)) {
+            f = fo;
+            id = io;
+        }
+    }
+}
+
+struct ArgminSmem {
+    double wf[16];
+    int wid[16];
+    double bf;
+    int bid;
+    int pad;
+    double bx[kMaxPar];
+};
+
+// Level-end argmin over every chain of the request (workgroups of one request
+// exchange candidates through device memory and a counter).  Afterwards every
+// thread sees the winner in s.bf / s.bx.  `round` counts exchanges; slots
+// alternate between two halves so that a fast workgroup can never overwrite
+// a slot another one has not read yet.
+template <int NP>
+__device__ inline void request_argmin(double f, int chain, bool active, const double *x, ArgminSmem &s,
+                               const ReqDesc &rq, int wg_local, int round, Cand *cands, uint32_t *bar,
+                               int req, int32_t *err) {
+    double wf = active ? f : __builtin_inf();
+    int wid = active ? chain : 0x7fffffff;
+    wave_argmin(wf, wid);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+        s.wf[wave] = wf;
+        s.wid[wave] = wid;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double bf = s.wf[0];
+        int bid = s.wid[0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+            if (s.wf[w] < bf || (s.wf[w] == bf && s.wid[w] < bid)) {
+                bf = s.wf[w];
+                bid = s.wid[w];
+            }
+        s.bf = bf;
+        s.bid = bid;
+    }
+    __syncthreads();
+    if (active && chain == s.bid) {
+#pragma unroll
+        for (int k = 0; k < NP; ++k) s.bx[k] = x[k];
+    }
+    __syncthreads();
+    if (rq.n_wg > 1) {
+        Cand *half = cands + rq.cand_off + (round & 1) * rq.n_wg;
+        if (threadIdx.x == 0) {
+            Cand &c = half[wg_local];
+            c.f = s.bf;
+            c.chain = s.bid;
+            for (int k = 0; k < NP; ++k) c.x[k] = s.bx[k];
+            __hip_atomic_fetch_add(&bar[req * kBarStride], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const uint32_t want = (uint32_t)(round + 1) * (uint32_t)rq.n_wg;
+            int spins = 0;
+            while (__hip_atomic_load(&bar[req * kBarStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > (1 << 24)) {
+                    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        // the first wave reads every candidate at once and takes their argmin
+        if (threadIdx.x < 64) {
+            double cf = __builtin_inf();
+            int cid = 0x7fffffff, cw = 0;
+            for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
+                const double fw = __hip_atomic_load(&half[w].f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const int iw = __hip_atomic_load(&half[w].chain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (fw < cf || (fw == cf && iw < cid)) {
+                    cf = fw;
+                    cid = iw;
+                    cw = w;
+                }
+            }
+            int key = cid;
+            double kf = cf;
+            wave_argmin(kf, key);
+            // the lane holding the winning chain id names its workgroup
+            const unsigned long long m = __ballot(cid == key && cf == kf);
+            const int src = __ffsll((long long)m) - 1;
+            const int bw = __shfl(cw, src, 64);
+            if (threadIdx.x < NP)
+                s.bx[threadIdx.x] = __hip_atomic_load(&half[bw].x[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (threadIdx.x == 0) {
+                s.bf = kf;
+                s.bid = key;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Levenberg-Marquardt polish in double from the annealing result (one wave
+// per request, lane = grid point).  Residuals r_j = (target - sigma_j) s_j;
+// Jacobian by central differences with h_k = 6e-6 (ub_k - lb_k) clamped to
+// the box; step (J^T J + lambda diag(J^T J)) d = -J^T r solved by Cholesky,
+// y = clamp(x + d); accept if f(y) < f(x) (lambda /= 10, floor 1e-15), else
+// lambda *= 10, up to 12 tries; at most 60 iterations; stop at f = 0, when no
+// damping helps, or when a step gains less than 1e-15 f.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T wave_sum_bcast(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return __shfl(v, 0, 64);   // one association order for every lane
+}
+
+// Sum of squared residuals at v over the lane's points; `ok` false if any
+// model vol is not finite and positive (or v is an infeasible case II vector).
+template <int MODEL, int FORMULA, bool BFREE>
+__device__ inline double lm_f(const double *v, const Pt<double> *pts, const Row<double> *rows, const int32_t *prow,
+                       int n_pts, const ReqDesc &rq, bool &ok) {
+    ModelEval<MODEL, FORMULA, double, BFREE> ev;
+    bool good = ev.init(v, rq.beta, rq.t_max);
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < n_pts && good; j += 64) {
+        ev.row(rows[prow[j]]);
+        const double sig = ev.point(pts[j]);
+        good &= vol_ok(sig);
+        const double e = fma(-sig, pts[j].sw, pts[j].tsw);
+        acc = fma(e, e, acc);
+    }
+    ok = __ballot(!good) == 0ull;
+    return wave_sum_bcast(acc);
+}
+
+template <int NP>
+__device__ __forceinline__ bool cholesky_solve(const double *A, const double *g, double lambda, double *d) {
+    double Mx[NP * NP], L[NP * NP], yv[NP];
+    double tr = 0.0;
+#pragma unroll
+    for (int k = 0; k < NP; ++k) tr += A[k * NP + k];
+    const double fl = 1e-12 * tr / NP + 1e-300;
+#pragma unroll
+    for (int a = 0; a < NP * NP; ++a) Mx[a] = A[a];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) Mx[k * NP + k] += lambda * fmax(A[k * NP + k], fl);
+#pragma unroll
+    for (int a = 0; a < NP; ++a)
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            double s = Mx[a * NP + b];
+#pragma unroll
+            for (int k = 0; k < b; ++k) s -= L[a * NP + k] * L[b * NP + k];
+            if (a == b) {
+                if (!(s > 0.0)) return false;
+                L[a * NP + a] = sqrt(s);
+            } else {
+                L[a * NP + b] = s / L[b * NP + b];
+            }
+        }
+#pragma unroll
+    for (int a = 0; a < NP; ++a) {
+        double s = -g[a];
+#pragma unroll
+        for (int k = 0; k < a; ++k) s -= L[a * NP + k] * yv[k];
+        yv[a] = s / L[a * NP + a];
+    }
+#pragma unroll
+    for (int a = NP - 1; a >= 0; --a) {
+        double s = yv[a];
+#pragma unroll
+        for (int k = a + 1; k < NP; ++k) s -= L[k * NP + a] * d[k];
+        d[a] = s / L[a * NP + a];
+    }
+    return true;
+}
+
+// One wave (threads 0..63 of the block) polishes x in place; returns f(x) and
+// counts objective evaluations in *ne.
+template <int MODEL, int FORMULA, bool BFREE>
+__device__ inline double lm_polish(double *xio, const Pt<double> *pts, const Row<double> *rows, const int32_t *prow,
+                            const ReqDesc &rq, unsigned long long *ne_out) {
+    constexpr int NP = base_npar<MODEL>() + (BFREE ? 1 : 0);
+    const int n = rq.n_pts;
+    double x[NP], lb[NP], ub[NP], h[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        x[k] = xio[k];
+        lb[k] = rq.lb[k];
+        ub[k] = rq.ub[k];
+        h[k] = 6e-6 * (ub[k] - lb[k]);
+    }
+    bool ok;
+    double fx = lm_f<MODEL, FORMULA, BFREE>(x, pts, rows, prow, n, rq, ok);
+    unsigned long long ne = 1;
+    if (!ok) fx = __builtin_inf();
+    double lambda = 1e-3;
+    for (int it = 0; it < 60 && fx > 0.0 && fx < __builtin_inf(); ++it) {
+        double A[NP * NP], g[NP];
+#pragma unroll
+        for (int a = 0; a < NP * NP; ++a) A[a] = 0.0;
+#pragma unroll
+        for (int a = 0; a < NP; ++a) g[a] = 0.0;
+        for (int j = threadIdx.x; j < n; j += 64) {
+            const Row<double> rw = rows[prow[j]];
+            const Pt<double> pj = pts[j];
+            ModelEval<MODEL, FORMULA, double, BFREE> ev;
+            ev.init(x, rq.beta, rq.t_max);
+            ev.row(rw);
+            const double r0 = fma(-ev.point(pj), pj.sw, pj.tsw);
+            double Jr[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) {
+                double xp[NP], xm[NP];
+#pragma unroll
+                for (int m = 0; m < NP; ++m) xp[m] = xm[m] = x[m];
+                xp[k] = fmin(fmax(x[k] + h[k], lb[k]), ub[k]);
+                xm[k] = fmin(fmax(x[k] - h[k], lb[k]), ub[k]);
+                const double den = xp[k] - xm[k];
+                ModelEval<MODEL, FORMULA, double, BFREE> ep, em;
+                const bool okp = ep.init(xp, rq.beta, rq.t_max), okm = em.init(xm, rq.beta, rq.t_max);
+                ep.row(rw);
+                em.row(rw);
+                const double sp = ep.point(pj), sm = em.point(pj);
+                const double rp = fma(-sp, pj.sw, pj.tsw), rm = fma(-sm, pj.sw, pj.tsw);
+                const bool good = okp && okm && den > 0.0 && vol_ok(sp) && vol_ok(sm);
+                Jr[k] = good ? (rp - rm) / den : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < NP; ++a) {
+                g[a] = fma(Jr[a], r0, g[a]);
+#pragma unroll
+                for (int b = 0; b < NP; ++b) A[a * NP + b] = fma(Jr[a], Jr[b], A[a * NP + b]);
+            }
+        }
+        ne += 2 * NP;
+#pragma unroll
+        for (int a = 0; a < NP * NP; ++a) A[a] = wave_sum_bcast(A[a]);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) g[a] = wave_sum_bcast(g[a]);
+        bool moved = false;
+        double fnew = fx;
+        for (int tries = 0; tries < 12; ++tries) {
+            double d[NP], y[NP];
+            if (cholesky_solve<NP>(A, g, lambda, d)) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) y[k] = fmin(fmax(x[k] + d[k], lb[k]), ub[k]);
+                bool oky;
+                const double fy = lm_f<MODEL, FORMULA, BFREE>(y, pts, rows, prow, n, rq, oky);
+                ++ne;
+                if (oky && fy < fx) {
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) x[k] = y[k];
+                    fnew = fy;
+                    lambda = fmax(lambda / 10.0, 1e-15);
+                    moved = true;
+                    break;
+                }
+            }
+            lambda *= 10.0;
+        }
+        if (!moved) break;
+        const double gain = fx - fnew;
+        fx = fnew;
+        if (gain <= 1e-15 * fx) break;
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) xio[k] = x[k];
+    *ne_out = ne;
+    return fx;
+}
+
+}  // namespace sabr

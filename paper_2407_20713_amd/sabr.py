@@ -25,7 +25,9 @@ SABR_W_ABSOLUTE, SABR_W_RELATIVE = 0, 1
 SABR_FP64, SABR_FP32 = 0, 1
 
 EXPORTED = ["sabr_ctx_create", "sabr_ctx_destroy", "sabr_ctx_last_error", "sabr_ctx_enable_timing",
-            "sabr_ctx_timing", "sabr_calibrate", "sabr_objective_batch", "sabr_mc_price"]
+            "sabr_ctx_timing", "sabr_calibrate", "sabr_objective_batch", "sabr_mc_price",
+            "sabr_server_create", "sabr_server_submit", "sabr_server_poll", "sabr_server_cancel",
+            "sabr_server_stats", "sabr_server_destroy"]
 
 _D = C.POINTER(C.c_double)
 _I32 = C.POINTER(C.c_int32)
@@ -104,6 +106,14 @@ def lib():
                                            C.c_void_p, C.c_void_p]
         L.sabr_mc_price.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem),
                                     C.POINTER(sabr_mc), C.c_int32, _D, _D]
+        L.sabr_server_create.argtypes = [C.c_void_p, C.c_int32, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]
+        L.sabr_server_submit.argtypes = [C.c_void_p, C.POINTER(sabr_request), C.POINTER(C.c_uint64)]
+        L.sabr_server_poll.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_uint64),
+                                       C.POINTER(sabr_result), _D, C.POINTER(C.c_int32)]
+        L.sabr_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
+        L.sabr_server_stats.argtypes = [C.c_void_p] + [C.POINTER(C.c_int64)] * 4 + [C.POINTER(C.c_int32)] + \
+                                       [C.POINTER(C.c_size_t)] * 2 + [C.POINTER(C.c_int32)]
+        L.sabr_server_destroy.argtypes = [C.c_void_p]
         _lib = L
     return _lib
 
@@ -281,3 +291,82 @@ def sabr_mc_price(ctx, market, problem, n_paths, steps_per_year=250, seed=0, pre
     mc = sabr_mc(n_paths, steps_per_year, seed)
     ctx.check(lib().sabr_mc_price(ctx.h, C.byref(m), C.byref(p), C.byref(mc), precision, _dp(price), _dp(se)))
     return price, se
+
+
+# --- serving -------------------------------------------------------------------
+class Server:
+    """Handle of a sabr_server (continuous batching of calibration requests)."""
+
+    def __init__(self, ctx, max_slots=64, hbm_budget_bytes=0, quantum_levels=10):
+        h = C.c_void_p()
+        ctx.check(lib().sabr_server_create(ctx.h, max_slots, hbm_budget_bytes, quantum_levels, C.byref(h)))
+        self.h, self.ctx = h, ctx
+
+    def submit(self, request):
+        t = C.c_uint64()
+        r = request.c()
+        self.ctx.check(lib().sabr_server_submit(self.h, C.byref(r), C.byref(t)))
+        return t.value
+
+    def poll(self, max_n=64, timeout_us=0):
+        """Finished requests as a list of (ticket, result dict, latency seconds)."""
+        tk = (C.c_uint64 * max_n)()
+        rs = (sabr_result * max_n)()
+        lat = (C.c_double * max_n)()
+        n = C.c_int32()
+        rc = lib().sabr_server_poll(self.h, max_n, timeout_us, tk, rs, lat, C.byref(n))
+        if rc not in (SABR_OK, SABR_E_TIMEOUT):
+            raise SabrError(rc, lib().sabr_ctx_last_error(self.ctx.h).decode())
+        out = []
+        for i in range(n.value):
+            o = rs[i]
+            out.append((tk[i], dict(x=np.array(o.x[:]), f=o.f, f_before_polish=o.f_before_polish,
+                                    n_evals=o.n_evals, n_accept=o.n_accept, status=o.status), lat[i]))
+        return out
+
+    def cancel(self, ticket):
+        self.ctx.check(lib().sabr_server_cancel(self.h, ticket))
+
+    def stats(self):
+        q, a, c, qu = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        act, pa = C.c_int32(), C.c_int32()
+        b, pb = C.c_size_t(), C.c_size_t()
+        self.ctx.check(lib().sabr_server_stats(self.h, C.byref(q), C.byref(a), C.byref(c), C.byref(qu),
+                                               C.byref(act), C.byref(b), C.byref(pb), C.byref(pa)))
+        return dict(quanta=q.value, admitted=a.value, completed=c.value, queued=qu.value, active=act.value,
+                    bytes_in_use=b.value, peak_bytes=pb.value, peak_active=pa.value)
+
+    def close(self):
+        if self.h:
+            lib().sabr_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sabr_server_create(ctx, max_slots=64, hbm_budget_bytes=0, quantum_levels=10):
+    return Server(ctx, max_slots, hbm_budget_bytes, quantum_levels)
+
+
+def sabr_server_submit(server, request):
+    return server.submit(request)
+
+
+def sabr_server_poll(server, max_n=64, timeout_us=0):
+    return server.poll(max_n, timeout_us)
+
+
+def sabr_server_cancel(server, ticket):
+    server.cancel(ticket)
+
+
+def sabr_server_stats(server):
+    return server.stats()
+
+
+def sabr_server_destroy(server):
+    server.close()

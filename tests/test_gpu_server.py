@@ -1,0 +1,151 @@
+"""GPU tests of the serving loop (sabr_server_*): each request's result is the
+same alone, in a mix and for another quantum length (bitwise), results match
+the oracle's calibration, admission respects the memory budget, and the
+error paths (cancel, poll timeout, unsupported request) behave."""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+from paper_2407_20713_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_2407_20713_amd import sabr
+    sabr.lib()
+    return sabr
+
+
+@pytest.fixture(scope="module")
+def ctx(S):
+    c = S.sabr_ctx_create(0)
+    yield c
+    c.close()
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_request(S, oracle, tr, n_chains, n_iters, mc_paths=512, polish=True):
+    """A serving request from a trace entry (targets from the oracle)."""
+    g = tr.grid
+    m = oracle.Market(g.T, g.fwd, g.offs, g.K, disc=g.disc)
+    if tr.kind == "static":
+        tgt = oracle.model_vols(m, oracle.STATIC, tr.x_true, 0.7) + tr.noise
+        lb, ub = inputs.box(inputs.STATIC)
+        req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                        precision=S.SABR_FP32, n_chains=n_chains, n_iters=n_iters, seed=tr.seed, polish=polish)
+    elif tr.kind == "dynamic":
+        tgt = oracle.model_vols(m, oracle.DYN_I, tr.x_true, 0.7) + tr.noise
+        lb, ub = inputs.box(inputs.DYN_I)
+        req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_DYN_I, 0.7, lb, ub),
+                        precision=S.SABR_FP32, n_chains=n_chains, n_iters=n_iters, seed=tr.seed, polish=polish)
+    else:
+        tgt, _ = oracle.mc_prices(m, oracle.STATIC, tr.x_true, 0.7, mc_paths, 250, tr.seed + 1)
+        tgt = np.maximum(tgt, 1e-6)
+        lb, ub = inputs.box(inputs.STATIC)
+        req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                        kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32,
+                        n_chains=min(n_chains, 64), n_iters=max(4, n_iters // 50), seed=tr.seed,
+                        n_paths=mc_paths, steps_per_year=50, mc_seed=tr.seed + 1)
+    return req, m, tgt
+
+
+def run_all(srv, reqs, timeout_s=120.0):
+    tickets = [srv.submit(r) for r in reqs]
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tickets) and time.time() - t0 < timeout_s:
+        for t, res, lat in srv.poll(64, 200000):
+            got[t] = (res, lat)
+    assert len(got) == len(tickets), "server did not finish in time"
+    return [got[t] for t in tickets]
+
+
+def small_trace(n, seed, max_mat=6):
+    tr = inputs.request_trace(n, 1000.0, seed=seed, max_mat=max_mat, strike_range=(5, 15))
+    return tr
+
+
+def test_alone_equals_mix_and_quantum(S, ctx, oracle):
+    trace = small_trace(18, 77)
+    kinds = [t.kind for t in trace]
+    say("kinds", kinds)
+    probe_by_kind = {}
+    for t in trace:
+        probe_by_kind.setdefault(t.kind, t)
+    assert set(probe_by_kind) == {"static", "dynamic", "mc"}
+    reqs = [build_request(S, oracle, t, 128 if t.kind == "static" else 96, 300)[0] for t in trace]
+    srv = S.Server(ctx, max_slots=32, quantum_levels=4)
+    mix = run_all(srv, reqs)
+    srv.close()
+    for kind, t in probe_by_kind.items():
+        i = trace.index(t)
+        srv1 = S.Server(ctx, max_slots=8, quantum_levels=7)
+        alone = run_all(srv1, [reqs[i]])[0][0]
+        srv1.close()
+        a, b = alone, mix[i][0]
+        say(kind, "alone", a["x"][:5], a["f"], "mix", b["x"][:5], b["f"])
+        assert a["status"] == 0 and b["status"] == 0
+        assert np.array_equal(a["x"], b["x"]) and a["f"] == b["f"] and a["n_accept"] == b["n_accept"]
+
+
+def test_server_result_matches_oracle_calibration(S, ctx, oracle):
+    """A static request served in FP32 with polish reaches the same least-squares
+    point as the oracle's FP64 calibration (both polished)."""
+    trace = small_trace(30, 5)
+    t = next(x for x in trace if x.kind == "static")
+    req, m, tgt = build_request(S, oracle, t, 128, 600)
+    srv = S.Server(ctx, max_slots=8, quantum_levels=10)
+    res = run_all(srv, [req])[0][0]
+    srv.close()
+    m.target = tgt
+    lb, ub = inputs.box(inputs.STATIC)
+    ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, 128, 600, t.seed, polish=True)
+    say("server", res["x"][:3], res["f"], "oracle", ref["x"], ref["f"])
+    np.testing.assert_allclose(res["x"][:3], ref["x"], atol=1e-3)
+    assert res["f"] <= ref["f"] * (1 + 1e-6) + 1e-14
+
+
+def test_budget_admission(S, ctx, oracle):
+    """With room for about two requests at a time every request still
+    completes and the arena never holds more than the budget."""
+    trace = [t for t in small_trace(40, 9) if t.kind == "static"][:6]
+    reqs = [build_request(S, oracle, t, 128, 200)[0] for t in trace]
+    budget = 2 * 1024 * 1024
+    srv = S.Server(ctx, max_slots=16, hbm_budget_bytes=budget, quantum_levels=5)
+    out = run_all(srv, reqs)
+    st = srv.stats()
+    srv.close()
+    say("stats", st)
+    assert all(r["status"] == 0 for r, _ in out)
+    assert st["peak_bytes"] <= budget
+    assert st["completed"] == len(reqs)
+
+
+def test_cancel_timeout_and_rejection(S, ctx, oracle):
+    srv = S.Server(ctx, max_slots=4, quantum_levels=2)
+    assert srv.poll(4, 1000) == []          # nothing submitted: times out
+    trace = [t for t in small_trace(40, 11) if t.kind == "static"][:3]
+    reqs = [build_request(S, oracle, t, 128, 4000)[0] for t in trace]
+    tickets = [srv.submit(r) for r in reqs]
+    srv.cancel(tickets[1])
+    got = {}
+    t0 = time.time()
+    while len(got) < 3 and time.time() - t0 < 120:
+        for t, res, lat in srv.poll(8, 200000):
+            got[t] = res
+    assert got[tickets[1]]["status"] == S.SABR_E_CANCELLED
+    assert got[tickets[0]]["status"] == 0 and got[tickets[2]]["status"] == 0
+    # FP64 requests are served by sabr_calibrate, not by the server
+    bad = build_request(S, oracle, trace[0], 64, 100)[0]
+    bad.obj.precision = S.SABR_FP64
+    with pytest.raises(S.SabrError) as e:
+        srv.submit(bad)
+    assert e.value.code == S.SABR_E_INVAL
+    srv.close()
