@@ -36,7 +36,7 @@ PEAK_VALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # transcendentals, 3 double ops = 21 + 12 + 6 = 39; and of one annealing
 # iteration outside the point loop (Philox4x32-10 with 20 32x32->64 multiplies
 # at quarter rate, the double proposal and the Metropolis test with its
-# double exp and division): ~200 slots.  Derivation in the design doc.
+# double exp and division): ~200 slots.
 SLOTS_PER_PT_EVAL = 39
 SLOTS_SA_PER_ITER = 200
 
@@ -119,9 +119,184 @@ def fp32_vs_oracle(S, ctx, reqs, results):
     return worst
 
 
+# --- other workloads (not the default line) ------------------------------------
+def bench_mc_calibration(S, inputs, ctx, args):
+    """Monte Carlo objective calibration: 8 quarterly maturities x 15 strikes,
+    static SABR (beta 0.7), targets from a 2^22-path FP64 run at the true
+    parameters, 1024 chains x `iters` iterations x 65536 common paths,
+    250 steps per year, relative squared price errors."""
+    g = inputs.mc_grid()
+    xt = g.meta["x_true"]
+    lb, ub = inputs.box(inputs.STATIC)
+    tgt, _ = S.sabr_mc_price(ctx, S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7, x0=xt), 1 << 22, 250,
+                             g.meta["target_seed"], precision=S.SABR_FP64)
+    iters = args.mc_iters
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=1024,
+                    n_iters=iters, cooling=0.99 ** (1000.0 / 500), seed=0x5AB30001, n_paths=65536,
+                    steps_per_year=250, mc_seed=g.meta["mc_seed"])
+    S.sabr_ctx_enable_timing(ctx, True)
+    S.sabr_ctx_timing(ctx, reset=True)
+    t = time.perf_counter()
+    res = S.sabr_calibrate(ctx, [req])[0]
+    wall = time.perf_counter() - t
+    ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
+    m_max = 500
+    cps = 1024 * 65536 * m_max * iters
+    return {"metric": "MC path-steps/s", "value": cps / wall, "unit": "chain-path-steps/s",
+            "kernel": name, "kernel_chain_path_steps_per_s": cps / (n and ms / 1e3 or 1),
+            "avg_kernel_ms": ms / max(n, 1), "launches": n, "wall_s": wall,
+            "config": {"workload": "MC-objective calibration, 8 x 15 calls, 1024 chains x %d iterations x 65536 "
+                                   "paths x 500 steps, FP32 paths" % iters},
+            "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"]}
+
+
+def bench_dynamic(S, inputs, ctx, args):
+    """Dynamic SABR case I, joint fit of 20 maturities x 20 strikes, 5
+    parameters, 8192 chains x `iters` iterations, FP32 bulk, polish."""
+    g = inputs.dynamic_surface()
+    xt = g.meta["x_true"]
+    lb, ub = inputs.box(inputs.DYN_I)
+    _, vol = S.sabr_objective_batch(ctx, S.Market.from_grid(g), S.Problem(S.SABR_DYN_I, 0.7), xt[None, :],
+                                    precision=S.SABR_FP64, want_model=True)
+    iters = args.dyn_iters
+    req = S.Request(S.Market.from_grid(g, target=vol[0]), S.Problem(S.SABR_DYN_I, 0.7, lb, ub),
+                    precision=S.SABR_FP32, n_chains=8192, n_iters=iters, cooling=0.99 ** (1000.0 / iters),
+                    seed=0x5AB40001, polish=True)
+    S.sabr_ctx_enable_timing(ctx, True)
+    S.sabr_calibrate(ctx, [req])
+    S.sabr_ctx_timing(ctx, reset=True)
+    t = time.perf_counter()
+    res = S.sabr_calibrate(ctx, [req])[0]
+    wall = time.perf_counter() - t
+    ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
+    pts = 8192 * iters * g.n_obs
+    return {"metric": "asymptotic-formula evals/s", "value": pts / wall, "unit": "point-evals/s",
+            "calibrations_per_s": 1.0 / wall, "kernel": name, "avg_kernel_ms": ms / max(n, 1), "wall_s": wall,
+            "config": {"workload": "dynamic SABR case I, 20 x 20 joint fit, 8192 chains x %d iterations" % iters},
+            "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"]}
+
+
+def serving_requests(S, inputs, ctx, n, rate, seed, mc_paths):
+    """Requests of the serving trace: 70 % static (256 chains x 2000), 20 %
+    dynamic case I (512 x 4000), 10 % Monte Carlo (64 x 100 x mc_paths),
+    targets = the library's FP64 model values at the drawn parameters plus
+    N(0, 1e-4) vol noise (Monte Carlo: FP64 prices from another seed)."""
+    trace = inputs.request_trace(n, rate, seed=seed)
+    reqs = []
+    for tr in trace:
+        g = tr.grid
+        if tr.kind == "mc":
+            lb, ub = inputs.box(inputs.STATIC)
+            tgt, _ = S.sabr_mc_price(ctx, S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7, x0=tr.x_true),
+                                     1 << 16, 250, tr.seed + 1, precision=S.SABR_FP32)
+            tgt = np.maximum(tgt, 1e-8)
+            req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                            kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=64,
+                            n_iters=100, seed=tr.seed, n_paths=mc_paths, steps_per_year=250, mc_seed=tr.seed + 2)
+        else:
+            model = S.SABR_STATIC if tr.kind == "static" else S.SABR_DYN_I
+            lb, ub = inputs.box(model)
+            _, vol = S.sabr_objective_batch(ctx, S.Market.from_grid(g), S.Problem(model, 0.7), tr.x_true[None, :],
+                                            precision=S.SABR_FP64, want_model=True)
+            tgt = vol[0] + tr.noise
+            chains, iters = (256, 2000) if tr.kind == "static" else (512, 4000)
+            req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(model, 0.7, lb, ub),
+                            precision=S.SABR_FP32, n_chains=chains, n_iters=iters, seed=tr.seed, polish=True)
+        reqs.append(req)
+    return trace, reqs
+
+
+def serve(S, ctx, trace, reqs, rate_scale, max_slots, quantum):
+    """Submit each request at its (scaled) arrival time; returns latencies and the makespan."""
+    srv = S.Server(ctx, max_slots=max_slots, hbm_budget_bytes=8 << 30, quantum_levels=quantum)
+    t0 = time.perf_counter()
+    lat, pending, i = [], 0, 0
+    while i < len(reqs) or pending:
+        now = time.perf_counter() - t0
+        while i < len(reqs) and trace[i].arrival_s * rate_scale <= now:
+            srv.submit(reqs[i])
+            i += 1
+            pending += 1
+        for t, res, l in srv.poll(256, 500):
+            lat.append(l)
+            pending -= 1
+            if len(lat) % 200 == 0:
+                print("served %d / %d" % (len(lat), len(reqs)), file=sys.stderr, flush=True)
+    span = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    return np.array(lat), span, st
+
+
+def bench_serving(S, inputs, ctx, args):
+    n = args.serve_requests
+    trace, reqs = serving_requests(S, inputs, ctx, n, 1.0, 0x5AB5, args.serve_paths)
+    # capacity: every request submitted at once
+    lat_b, span_b, st_b = serve(S, ctx, trace, reqs, 0.0, args.serve_slots, args.serve_quantum)
+    capacity = n / span_b
+    # Poisson arrivals at 0.8 x capacity (the trace is drawn at rate 1; scale its times)
+    lat_s, span_s, st_s = serve(S, ctx, trace, reqs, 1.0 / (0.8 * capacity), args.serve_slots, args.serve_quantum)
+    # baseline: the same trace, one sabr_calibrate call per request, FIFO, same arrival times
+    t0 = time.perf_counter()
+    lat_1 = []
+    for tr, r in zip(trace, reqs):
+        arr = tr.arrival_s / (0.8 * capacity)
+        now = time.perf_counter() - t0
+        if now < arr:
+            time.sleep(arr - now)
+        S.sabr_calibrate(ctx, [r])
+        lat_1.append(time.perf_counter() - t0 - arr)
+        if len(lat_1) % 200 == 0:
+            print("one-per-launch %d / %d" % (len(lat_1), len(reqs)), file=sys.stderr, flush=True)
+    span_1 = time.perf_counter() - t0
+    lat_1 = np.array(lat_1)
+    kinds = {k: sum(1 for t in trace if t.kind == k) for k in ("static", "dynamic", "mc")}
+    return {"metric": "calibrations/s + p50/p99 latency", "value": n / span_s, "unit": "calibrations/s",
+            "config": {"workload": "serving trace: %d requests, Poisson arrivals at 0.8 x measured capacity, "
+                                   "1-20 maturities x 5-41 strikes, mix %s, Monte Carlo %d paths" % (
+                                       n, kinds, args.serve_paths),
+                       "slots": args.serve_slots, "quantum_levels": args.serve_quantum},
+            "capacity_calibrations_per_s": capacity,
+            "served": {"calibrations_per_s": n / span_s, "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat_s, 99) * 1e3), "peak_active": st_s["peak_active"],
+                       "peak_bytes": st_s["peak_bytes"], "quanta": st_s["quanta"]},
+            "one_request_per_launch": {"calibrations_per_s": n / span_1,
+                                       "p50_ms": float(np.percentile(lat_1, 50) * 1e3),
+                                       "p99_ms": float(np.percentile(lat_1, 99) * 1e3)}}
+
+
+def bench_copy(S, inputs, ctx, args):
+    """Reference for the HBM byte counters: a plain device-to-device copy of
+    a known size (read once, written once)."""
+    import torch
+    n = args.copy_mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / reps
+    return {"metric": "copy bandwidth", "value": 2 * n / dt / 1e9, "unit": "GB/s", "bytes_read": n,
+            "bytes_written": n, "config": {"workload": "device copy of %d MiB" % args.copy_mib}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", default="surface", choices=["surface", "mc_calibration", "dynamic", "serving", "copy"])
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--mc-iters", type=int, default=500)
+    ap.add_argument("--dyn-iters", type=int, default=50000)
+    ap.add_argument("--serve-requests", type=int, default=10000)
+    ap.add_argument("--serve-paths", type=int, default=16384)
+    ap.add_argument("--serve-slots", type=int, default=1024)
+    ap.add_argument("--serve-quantum", type=int, default=20)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -138,6 +313,14 @@ def main():
 
     S.lib()
     ctx = S.sabr_ctx_create(0)
+    if args.workload != "surface":
+        fn = {"mc_calibration": bench_mc_calibration, "dynamic": bench_dynamic, "serving": bench_serving,
+              "copy": bench_copy}
+        out = fn[args.workload](S, inputs, ctx, args)
+        out.update({"n_gpus": 1, "data": "synthetic", "higher_is_better": True})
+        ctx.close()
+        print(json.dumps(out))
+        return
     reqs, truths = build_requests(S, inputs, ctx, S.SABR_FP32)
     S.sabr_ctx_enable_timing(ctx, True)
     for _ in range(args.warmup):

@@ -202,16 +202,17 @@ int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *
  * A worker thread owns a device-resident table of max_slots slots.  A
  * submitted request waits in a FIFO queue until a slot of its kind is free
  * and its device footprint (grid, schedule, chain state, Monte Carlo
- * partials) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each quantum is
- * one replay of a captured HIP graph that normalises new grids, advances
- * every formula slot by quantum_levels temperature levels and every Monte
- * Carlo slot by one iteration, and copies the slot states back; requests
- * admitted while others run join at the next quantum.  Slots 0..max_slots/8-1
+ * partials) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each quantum
+ * replays captured HIP graphs that normalise new grids, advance every
+ * formula slot by quantum_levels temperature levels and, on a second stream
+ * at the same time, every Monte Carlo slot by max(1, quantum_levels / 5)
+ * iterations, and copy the slot states back; requests admitted while others
+ * run join at the next quantum.  Slots 0..max_slots/8-1
  * take Monte Carlo requests, the others formula requests.
  *
  * Supported requests: FP32 precision, fixed beta, and either the static
  * Hagan formula (<= 256 chains), the dynamic case I formula (<= 512 chains)
- * or the static Monte Carlo objective (<= 64 chains, <= 512 options);
+ * or the static Monte Carlo objective (<= 64 chains, <= 600 options);
  * grids up to 1024 points and 32 maturities.  Others: SABR_E_INVAL (use
  * sabr_calibrate).  A request's result depends only on the request (its
  * random words are keyed by its seed and chain ids, its sums run in a fixed

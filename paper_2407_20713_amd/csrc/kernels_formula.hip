@@ -98,14 +98,18 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
     const bool active = chain < rq.n_chains;
     const int n_mat = rq.n_mat, L = rq.chain_len, n_iters = rq.n_iters;
     const double beta = rq.beta, tmax = rq.t_max;
+    const int rsplit = rq.rsplit;
     const uint32_t k0 = rq.key0, k1 = rq.key1;
     auto f_of = [&](const double *v) {
-        double part = objective<MODEL, FORMULA, R, BFREE, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub);
-        if constexpr (LPC == 2) part = part + __shfl_xor(part, 1, 64);
+        double part = objective<MODEL, FORMULA, R, BFREE, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub,
+                                                                      rsplit);
+        // butterfly over the lane group: every lane ends with the same bits
+#pragma unroll
+        for (int off = 1; off < LPC; off <<= 1) part = part + __shfl_xor(part, off, 64);
         return part;
     };
 
-    double x[NP], bx[NP], y[NP];
+    double x[NP], bx[NP];
 #pragma unroll
     for (int k = 0; k < NP; ++k) x[k] = bx[k] = rq.x0[k];
     double fx = f_of(x);
@@ -119,33 +123,7 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
         const double h = sched_h[rq.sched_off + lev];
         const double Tk = T0 * g;
         const int t1 = min((lev + 1) * L, n_iters);
-        if (active) {
-            for (int t = lev * L; t < t1; ++t) {
-                double u[NB * 4];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const uint4 w = philox4x32_10(make_uint4((uint32_t)chain, (uint32_t)t, (uint32_t)b, 1u), k0, k1);
-                    u[4 * b + 0] = unit_u32(w.x);
-                    u[4 * b + 1] = unit_u32(w.y);
-                    u[4 * b + 2] = unit_u32(w.z);
-                    u[4 * b + 3] = unit_u32(w.w);
-                }
-#pragma unroll
-                for (int k = 0; k < NP; ++k) y[k] = propose_coord(x[k], u[k], h, s_lb[k], s_ub[k]);
-                const double fy = f_of(y);
-                if (metropolis(fy, fx, u[NP], Tk)) {
-#pragma unroll
-                    for (int k = 0; k < NP; ++k) x[k] = y[k];
-                    fx = fy;
-                    ++nacc;
-                    if (fy < fb) {
-                        fb = fy;
-#pragma unroll
-                        for (int k = 0; k < NP; ++k) bx[k] = y[k];
-                    }
-                }
-            }
-        }
+        if (active) sa_level<NP, NB, LPC, R>(chain, sub, lev * L, t1, k0, k1, h, Tk, s_lb, s_ub, x, fx, bx, fb, nacc, f_of);
         request_argmin<NP>(fx, chain, active, x, am, rq, wg_local, round++, cands, bar, req, err);
         fx = am.bf;
 #pragma unroll
@@ -258,11 +236,25 @@ const void *sa_kernel_ptr(int model, int formula, bool fp32, bool bfree, int lpc
         SABR_FORMULA_VARIANTS(SABR_P)
 #undef SABR_P
     };
+    // wide lane groups: float dynamic models only (few chains, many rows)
+#define SABR_WIDE(MD, BF)                                                                          \
+    {(const void *)sa_kernel<MD, F_HAGAN, float, BF, 4>, (const void *)sa_kernel<MD, F_HAGAN, float, BF, 8>, \
+     (const void *)sa_kernel<MD, F_HAGAN, float, BF, 16>}
+    static const void *wide[4][3] = {SABR_WIDE(MODEL_DYN_I, false), SABR_WIDE(MODEL_DYN_I, true),
+                                     SABR_WIDE(MODEL_DYN_II, false), SABR_WIDE(MODEL_DYN_II, true)};
+#undef SABR_WIDE
     const int v = variant_index(model, formula, bfree);
     if (v < 0) return nullptr;
     if (lpc == 2) return fp32 ? tab32x2[v] : tab64x2[v];
-    return fp32 ? tab32[v] : tab64[v];
+    if (lpc == 4 || lpc == 8 || lpc == 16) {
+        if (!fp32 || model == MODEL_STATIC) return nullptr;
+        const int w = (model == MODEL_DYN_II ? 2 : 0) + (bfree ? 1 : 0);
+        return wide[w][lpc == 4 ? 0 : (lpc == 8 ? 1 : 2)];
+    }
+    return lpc == 1 ? (fp32 ? tab32[v] : tab64[v]) : nullptr;
 }
+
+bool wide_lanes_supported(int model, bool fp32) { return fp32 && model != MODEL_STATIC; }
 
 const void *polish_kernel_ptr(int model, int formula, bool bfree) {
     static const void *tab[] = {

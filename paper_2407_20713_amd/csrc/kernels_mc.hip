@@ -123,12 +123,13 @@ __global__ void __launch_bounds__(64) mc_crn_kernel(McCrnDesc d, const double *Y
     crn_block<MODEL>(d, blockIdx.x / d.n_pblocks, blockIdx.x % d.n_pblocks, Y, mat_steps, offs, K, part, smem);
 }
 
-__global__ void mc_crn_reduce(McCrnDesc d, const double *Y, const float *part, const int32_t *obs_row,
-                              const double *disc, const double *target, const double *sw, double *f,
-                              double *model, int write_f) {
-    const int64_t chain = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (chain >= d.n_chains) return;
-    crn_reduce_chain(d, chain, Y, part, obs_row, disc, target, sw, f, model, write_f);
+__global__ void __launch_bounds__(1024) mc_crn_reduce(McCrnDesc d, const double *Y, const float *part,
+                                                     const int32_t *obs_row, const double *disc,
+                                                     const double *target, const double *sw, double *f,
+                                                     double *model, int write_f) {
+    __shared__ double s_acc[1024];
+    __shared__ int s_bad[1024];
+    crn_reduce_tile(d, blockIdx.x, Y, part, obs_row, disc, target, sw, f, model, write_f, s_acc, s_bad);
 }
 
 // ---------------------------------------------------------------------------

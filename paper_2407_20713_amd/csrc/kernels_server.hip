@@ -49,15 +49,12 @@ __global__ void __launch_bounds__(256) slot_prepare_kernel(SlotDev *slots, int n
 // polished by the first wave (double-precision Levenberg-Marquardt).
 // ---------------------------------------------------------------------------
 template <int KIND>
-__global__ void __launch_bounds__(kSlotThreads, 1) sa_slot_kernel(SlotDev *slots, int Q) {
+__device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
     constexpr int MODEL = KIND == KIND_STATIC ? MODEL_STATIC : MODEL_DYN_I;
     constexpr int FORMULA = F_HAGAN;
     constexpr int LPC = KIND == KIND_STATIC ? 2 : 1;
     constexpr int NP = base_npar<MODEL>();
     constexpr int NB = (NP + 1 + 3) / 4;
-    SlotDev &s = slots[blockIdx.x];
-    if (s.kind != KIND || (s.state != SLOT_READY && s.state != SLOT_RUNNING)) return;
-    extern __shared__ unsigned char smem[];
     const ReqDesc &rq = s.rq;
     ArgminSmem &am = *reinterpret_cast<ArgminSmem *>(smem);
     double *s_lb = reinterpret_cast<double *>(smem + sizeof(ArgminSmem));
@@ -83,7 +80,7 @@ __global__ void __launch_bounds__(kSlotThreads, 1) sa_slot_kernel(SlotDev *slots
         if constexpr (LPC == 2) part = part + __shfl_xor(part, 1, 64);
         return part;
     };
-    double x[NP], bx[NP], y[NP];
+    double x[NP], bx[NP];
     double fx, fb, T0;
     unsigned long long nacc = 0;
     const int lev0 = s.level;
@@ -110,33 +107,9 @@ __global__ void __launch_bounds__(kSlotThreads, 1) sa_slot_kernel(SlotDev *slots
         const double h = s.sched_h[lev];
         const double Tk = T0 * s.sched_g[lev];
         const int t1 = min((lev + 1) * L, n_iters);
-        if (active) {
-            for (int t = lev * L; t < t1; ++t) {
-                double u[NB * 4];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    const uint4 w = philox4x32_10(make_uint4((uint32_t)chain, (uint32_t)t, (uint32_t)b, 1u), rq.key0, rq.key1);
-                    u[4 * b + 0] = unit_u32(w.x);
-                    u[4 * b + 1] = unit_u32(w.y);
-                    u[4 * b + 2] = unit_u32(w.z);
-                    u[4 * b + 3] = unit_u32(w.w);
-                }
-#pragma unroll
-                for (int k = 0; k < NP; ++k) y[k] = propose_coord(x[k], u[k], h, s_lb[k], s_ub[k]);
-                const double fy = f_of(y);
-                if (metropolis(fy, fx, u[NP], Tk)) {
-#pragma unroll
-                    for (int k = 0; k < NP; ++k) x[k] = y[k];
-                    fx = fy;
-                    ++nacc;
-                    if (fy < fb) {
-                        fb = fy;
-#pragma unroll
-                        for (int k = 0; k < NP; ++k) bx[k] = y[k];
-                    }
-                }
-            }
-        }
+        if (active)
+            sa_level<NP, NB, LPC, float>(chain, sub, lev * L, t1, rq.key0, rq.key1, h, Tk, s_lb, s_ub, x, fx, bx, fb,
+                                         nacc, f_of);
         request_argmin<NP>(fx, chain, active, x, am, rq, 0, 0, nullptr, nullptr, 0, nullptr);
         fx = am.bf;
 #pragma unroll
@@ -211,6 +184,19 @@ __global__ void __launch_bounds__(kSlotThreads, 1) sa_slot_kernel(SlotDev *slots
     }
 }
 
+// One launch for every formula slot (slots [first, first + gridDim.x)): each
+// workgroup runs the body of its slot's kind, so static and dynamic requests
+// share the chip within one quantum.
+__global__ void __launch_bounds__(kSlotThreads, 1) sa_slot_kernel(SlotDev *slots, int first, int Q) {
+    SlotDev &s = slots[first + blockIdx.x];
+    if (s.state != SLOT_READY && s.state != SLOT_RUNNING) return;
+    extern __shared__ unsigned char smem[];
+    if (s.kind == KIND_STATIC)
+        sa_slot_body<KIND_STATIC>(s, Q, smem);
+    else if (s.kind == KIND_DYN_I)
+        sa_slot_body<KIND_DYN_I>(s, Q, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Monte Carlo slots (Technique II on the device): one iteration of every
 // running Monte Carlo slot is three kernels: common-random-number paths for
@@ -221,22 +207,24 @@ __device__ __forceinline__ bool mc_slot_live(const SlotDev &s) {
     return s.kind == KIND_MC && (s.state == SLOT_READY || s.state == SLOT_RUNNING) && s.iter < s.sa.n_iters;
 }
 
-__global__ void __launch_bounds__(64) mc_slot_crn_kernel(SlotDev *slots) {
+// Slots whose option count falls in LDS class `cls` (see mc_slot_class).
+__global__ void __launch_bounds__(64) mc_slot_crn_kernel(SlotDev *slots, int cls) {
     SlotDev &s = slots[blockIdx.x / kMcPBlocks];
-    if (!mc_slot_live(s)) return;
+    if (!mc_slot_live(s) || mc_slot_class(s.crn.n_obs) != cls) return;
     extern __shared__ unsigned char smem[];
     McCrnDesc d = s.crn;
     if (s.iter < 0) d.n_chains = 1;   // f(x0) from Y[0] = x0
     crn_block<MODEL_STATIC>(d, 0, blockIdx.x % kMcPBlocks, s.Y, s.msteps, s.offs, s.K, s.part, smem);
 }
 
-__global__ void __launch_bounds__(64) mc_slot_reduce_kernel(SlotDev *slots) {
+__global__ void __launch_bounds__(1024) mc_slot_reduce_kernel(SlotDev *slots) {
     SlotDev &s = slots[blockIdx.x];
     if (!mc_slot_live(s)) return;
+    __shared__ double s_acc[1024];
+    __shared__ int s_bad[1024];
     McCrnDesc d = s.crn;
     if (s.iter < 0) d.n_chains = 1;
-    if (threadIdx.x < d.n_chains)
-        crn_reduce_chain(d, threadIdx.x, s.Y, s.part, s.obsrow, s.disc, s.target, s.sw, s.fy, nullptr, 1);
+    crn_reduce_tile(d, 0, s.Y, s.part, s.obsrow, s.disc, s.target, s.sw, s.fy, nullptr, 1, s_acc, s_bad);
 }
 
 __global__ void __launch_bounds__(256) mc_slot_step_kernel(SlotDev *slots) {
@@ -281,9 +269,7 @@ __global__ void slot_status_kernel(const SlotDev *slots, int n_slots, SlotStatus
 }
 
 const void *slot_prepare_kernel_ptr() { return (const void *)slot_prepare_kernel; }
-const void *sa_slot_kernel_ptr(int kind) {
-    return kind == KIND_STATIC ? (const void *)sa_slot_kernel<KIND_STATIC> : (const void *)sa_slot_kernel<KIND_DYN_I>;
-}
+const void *sa_slot_kernel_ptr() { return (const void *)sa_slot_kernel; }
 const void *mc_slot_crn_kernel_ptr() { return (const void *)mc_slot_crn_kernel; }
 const void *mc_slot_reduce_kernel_ptr() { return (const void *)mc_slot_reduce_kernel; }
 const void *mc_slot_step_kernel_ptr() { return (const void *)mc_slot_step_kernel; }

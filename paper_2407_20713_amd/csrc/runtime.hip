@@ -48,7 +48,8 @@ struct sabr_ctx {
     std::string kernel_name;
     std::vector<EventPair> pending;
     std::vector<EventPair> pool;
-    int force_lpc = 0;   // SABR_LANES_PER_CHAIN overrides the choice (1 or 2)
+    int force_lpc = 0;      // SABR_LANES_PER_CHAIN overrides the choice (1, 2, 4, 8 or 16)
+    int force_rsplit = 0;   // SABR_ROW_SPLIT overrides the row split of a lane group (1 .. 16)
     // pinned staging for host-to-device copies: valid until the next sync
     unsigned char *stage = nullptr;
     size_t stage_bytes = 0, stage_used = 0;
@@ -456,11 +457,31 @@ struct Group {
 
 // Lanes per chain, a property of the request alone (so that its result never
 // depends on the other requests of a batch): requests of 1024 chains or more
-// split each chain's strikes over two lanes, which doubles the waves of the
-// few-but-large requests that would otherwise leave SIMDs half idle.
+// split each chain's work over two lanes, which doubles the waves of the
+// few-but-large requests that would otherwise leave SIMDs half idle.  Float
+// dynamic requests (many maturity rows, each with its own integrals) widen
+// the group up to 16 lanes while the request stays within two waves per SIMD
+// of the whole chip (131072 lanes) and the group within twice its rows.
 int lanes_per_chain(const sabr_ctx *c, const sabr_request &q) {
-    if (c->force_lpc) return c->force_lpc;
-    return q.sa.n_chains >= 1024 ? 2 : 1;
+    const bool wide = wide_lanes_supported(q.problem.model, q.obj.precision == SABR_FP32);
+    if (c->force_lpc) return c->force_lpc > 2 && !wide ? 2 : c->force_lpc;
+    if (q.sa.n_chains < 1024) return 1;
+    int lpc = 2;
+    if (wide)
+        while (lpc < 16 && (int64_t)q.sa.n_chains * lpc * 2 <= 131072 && lpc * 2 <= 2 * q.market.n_mat) lpc *= 2;
+    return lpc;
+}
+
+// Lanes of a group that split the maturity rows (the rest split the strikes of
+// a row): all of them while the rows are at least four per lane, else the
+// largest power of two that leaves four rows per lane.  The static z-form
+// formulas split strikes only.
+int row_split(const sabr_ctx *c, const sabr_request &q, int lpc) {
+    if (lpc == 1 || q.problem.model == SABR_STATIC) return 1;
+    if (c->force_rsplit) return std::min(c->force_rsplit, lpc);
+    int rs = 1;
+    while (rs < lpc && 4 * (rs * 2) <= q.market.n_mat) rs *= 2;
+    return rs;
 }
 
 int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, sabr_result *out) {
@@ -484,6 +505,7 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
         d.n_levels = (q.sa.n_iters + q.sa.chain_len - 1) / q.sa.chain_len;
         d.sched_off = (int)sg.size();
         d.polish = q.sa.polish;
+        d.rsplit = row_split(c, q, lpc);
         d.key0 = (uint32_t)(q.sa.seed & 0xffffffffu);
         d.key1 = (uint32_t)(q.sa.seed >> 32);
         d.T0 = q.sa.T0;
@@ -678,7 +700,7 @@ int mc_objective_device(sabr_ctx *c, const McGrid &g, int model, int n_par, int 
     const double *tgp = want_f ? tg : nullptr;
     int wf = want_f ? 1 : 0;
     void *a2[] = {&d, &Ydev, &part, &orow, &disc, &tgp, &sw, &fdev, &modeldev, &wf};
-    return launch(c, false, "mc_crn_reduce", mc_crn_reduce_ptr(), dim3((unsigned)((n_x + 255) / 256)), dim3(256), a2, 0);
+    return launch(c, false, "mc_crn_reduce", mc_crn_reduce_ptr(), dim3((unsigned)tiles), dim3(1024), a2, 0);
 }
 
 int run_mc_request(sabr_ctx *c, const sabr_request &q, sabr_result &out) {
@@ -789,7 +811,11 @@ int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx 
     c->n_cu = prop.multiProcessorCount;
     if (const char *e = std::getenv("SABR_LANES_PER_CHAIN")) {
         const int v = std::atoi(e);
-        c->force_lpc = (v == 1 || v == 2) ? v : 0;
+        c->force_lpc = (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) ? v : 0;
+    }
+    if (const char *e = std::getenv("SABR_ROW_SPLIT")) {
+        const int v = std::atoi(e);
+        c->force_rsplit = (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) ? v : 0;
     }
     int smem = 0;
     hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device);

@@ -39,6 +39,8 @@ struct ReqDesc {
     int32_t wg_first, n_wg;   // workgroups of this request in the launch
     int32_t cand_off;     // first candidate slot (2 * n_wg slots)
     int32_t polish;
+    int32_t rsplit;       // lanes per chain that split the maturity rows (divides the lane count)
+    int32_t pad_r;
     uint32_t key0, key1;
     double beta;
     double T0;            // <= 0: f(x0)

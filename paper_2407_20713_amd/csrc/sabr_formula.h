@@ -237,11 +237,15 @@ __device__ __forceinline__ bool vol_ok(R sig) { return sig > (R)0 && sig < (R)__
 // sum over points of ((target - model) * sw)^2, accumulated in double.
 // A model vol that is not finite and positive, or an infeasible case II
 // vector, gives +inf.  WRITE stores the model vols to out[0..n_pts).
-// With LPC > 1 lanes per parameter vector, lane `sub` takes the points
-// p0 + sub, p0 + sub + LPC, ... of every row and returns its partial sum.
+// With LPC > 1 lanes per parameter vector, lane `sub` returns a partial sum.
+// The static z-form loop splits the points of every row over the lanes; the
+// other formulas split the rows over `rsplit` lanes (lane sub % rsplit takes
+// rows i = sub % rsplit (mod rsplit)) and the points of each row over the
+// remaining LPC / rsplit lanes, so that a row's integrals are computed by
+// fewer lanes than its points.
 template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE, int LPC = 1>
 __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
-                            double beta_fixed, double t_max, double *out, int sub = 0) {
+                            double beta_fixed, double t_max, double *out, int sub = 0, int rsplit = 1) {
     ModelEval<MODEL, FORMULA, R, BFREE> ev;
     if (!ev.init(y, beta_fixed, t_max)) return __builtin_inf();
     double acc = 0.0;
@@ -272,7 +276,7 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
                 const float ca = fmaf(fmaf(c1a2, pa.Q2, fmaf(c2rna, pa.Q1, c3n2)), pa.T, 1.0f);
                 const float cb = fmaf(fmaf(c1a2, pb.Q2, fmaf(c2rna, pb.Q1, c3n2)), pb.T, 1.0f);
                 const float sa = alf * pa.P1 * zxa * ca, sb = alf * pb.P1 * zxb * cb;
-                bad |= !vol_ok(sa) | !vol_ok(sb);
+                bad |= !vol_ok(sa) || !vol_ok(sb);
                 const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
                 acc = fma(ea, ea, acc);
                 acc = fma(eb, eb, acc);
@@ -287,10 +291,12 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
         }
         return bad ? __builtin_inf() : acc;
     }
-    for (int i = 0; i < n_mat; ++i) {
+    const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
+    const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
+    for (int i = rsub; i < n_mat; i += RS) {
         const Row<R> rw = rows[i];
         ev.row(rw);
-        for (int j = rw.p0 + sub; j < rw.p1; j += LPC) {
+        for (int j = rw.p0 + psub; j < rw.p1; j += PS) {
             const Pt<R> p = pts[j];
             const R sig = ev.point(p);
             bad |= !vol_ok(sig);

@@ -47,6 +47,7 @@ const void *prepare_points_kernel_ptr();
 const void *prepare_mats_kernel_ptr();
 const void *objective_kernel_ptr(int model, int formula, bool fp32, bool bfree);
 const void *sa_kernel_ptr(int model, int formula, bool fp32, bool bfree, int lpc);
+bool wide_lanes_supported(int model, bool fp32);   // 4, 8 or 16 lanes per chain
 const void *polish_kernel_ptr(int model, int formula, bool bfree);
 size_t grid_smem_bytes(bool fp32, int n_pts, int n_mat);
 size_t sa_smem_fixed_bytes();

@@ -81,9 +81,39 @@ __device__ __forceinline__ double mc_propose(double x, double u, double h, doubl
     return y;
 }
 
+// Step coefficients at time t in float, from float parameters (the Monte
+// Carlo objective of the dynamic models evaluates them every step).
 template <int MODEL>
+__device__ __forceinline__ StepC<float> step_coeffs_f(const float *xf, float t, float sdt, float ndt) {
+    constexpr float kLog2e = 1.4426950408889634f;
+    float nu, rho;
+    if constexpr (MODEL == MODEL_DYN_I) {
+        nu = xf[2] * __builtin_amdgcn_exp2f(-xf[4] * t * kLog2e);
+        rho = xf[1] * __builtin_amdgcn_exp2f(-xf[3] * t * kLog2e);
+    } else {
+        nu = fmaf(xf[8], t, xf[2]) * __builtin_amdgcn_exp2f(-xf[4] * t * kLog2e) + xf[6];
+        rho = fmaf(xf[7], t, xf[1]) * __builtin_amdgcn_exp2f(-xf[3] * t * kLog2e) + xf[5];
+    }
+    StepC<float> c;
+    c.nz = nu * sdt;
+    c.nd = nu * nu * ndt;
+    c.rz = rho * sdt;
+    c.rp = __builtin_amdgcn_sqrtf(fmaxf(1.0f - rho * rho, 0.0f)) * sdt;
+    return c;
+}
+
+// Common-random-number pricing of one wave: lane = one parameter vector of
+// the tile, the wave walks the paths [pb * ppb, (pb + 1) * ppb) NPATH at a
+// time so that every lane carries NPATH independent recurrences.  The
+// normals of a step are made once per wave (lane q * LPP + j draws the
+// Philox block (path q, step pair j) and turns both of its pairs into
+// normals) and broadcast to all lanes; payoffs go to per-lane float sums in
+// LDS, one per option.
+template <int MODEL, int NPATH = 2>
 __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const double *Y, const int32_t *mat_steps,
                           const int32_t *offs, const double *K, float *part, unsigned char *smem) {
+    constexpr int LPP = 64 / NPATH;          // lanes per path when drawing normals
+    constexpr int CH = 2 * LPP;              // steps per chunk
     float *Ks = reinterpret_cast<float *>(smem);
     float *acc = Ks + ((d.n_obs + 3) / 4) * 4;        // [n_obs][64]
     const int lane = threadIdx.x;
@@ -93,43 +123,66 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
     const bool active = chain < d.n_chains;
     constexpr int NP = MODEL == MODEL_STATIC ? 3 : (MODEL == MODEL_DYN_I ? 5 : 9);
     double x[NP];
-    for (int k = 0; k < NP; ++k) x[k] = active ? Y[chain * d.np_stride + k] : (k == 0 ? 0.2 : 0.0);
+    float xf[NP];
+    for (int k = 0; k < NP; ++k) {
+        x[k] = active ? Y[chain * d.np_stride + k] : (k == 0 ? 0.2 : 0.0);
+        xf[k] = (float)x[k];
+    }
     const double beta = d.beta_free ? (active ? Y[chain * d.np_stride + NP] : 1.0) : d.beta;
     const float bm1 = (float)(beta - 1.0);
     const float hd = (float)(d.dt / (2.0 * kLn2));
     const float xabs = (float)kLog2Abs;
     const float A0 = (float)(log2(x[0]) + (beta - 1.0) * log2(d.f0));
-    StepC<float> cst = step_coeffs<float>(MODEL_STATIC, x, 0.0, d.dt);
+    const StepC<float> cst = step_coeffs<float>(MODEL_STATIC, x, 0.0, d.dt);
+    const float sdt = (float)(sqrt(d.dt) / kLn2), ndt = (float)(-d.dt / (2.0 * kLn2)), dtf = (float)d.dt;
     const float f0 = (float)d.f0;
+    const int q_self = lane / LPP, j_self = lane % LPP;
     __syncthreads();
     const int64_t p_begin = (int64_t)pb * d.paths_per_block;
     const int64_t p_end = min<int64_t>(p_begin + d.paths_per_block, d.n_paths);
-    for (int64_t path = p_begin; path < p_end; ++path) {
-        float X = 0.0f, A = A0;
+    for (int64_t path = p_begin; path < p_end; path += NPATH) {
+        const int n_live = (int)min<int64_t>(NPATH, p_end - path);
+        float X[NPATH], A[NPATH];
+#pragma unroll
+        for (int q = 0; q < NPATH; ++q) {
+            X[q] = 0.0f;
+            A[q] = A0;
+        }
         int mi = 0;
         int mnext = mat_steps[0];
-        for (int s0 = 0; s0 < d.m_max; s0 += 64) {
-            const int s = s0 + lane;
-            const uint4 w = philox4x32_10(make_uint4((uint32_t)path, (uint32_t)(s >> 1), 0u, 2u), d.key0, d.key1);
-            float z1l, z2l;
-            MC<float>::normals(unit_u24f((s & 1) ? w.z : w.x), unit_u24f((s & 1) ? w.w : w.y), z1l, z2l);
-            const int n_here = min(64, d.m_max - s0);
+        for (int s0 = 0; s0 < d.m_max; s0 += CH) {
+            const uint4 w = philox4x32_10(make_uint4((uint32_t)(path + q_self), (uint32_t)((s0 >> 1) + j_self), 0u, 2u),
+                                          d.key0, d.key1);
+            float ze1, ze2, zo1, zo2;
+            MC<float>::normals(unit_u24f(w.x), unit_u24f(w.y), ze1, ze2);
+            MC<float>::normals(unit_u24f(w.z), unit_u24f(w.w), zo1, zo2);
+            const int n_here = min(CH, d.m_max - s0);
 #pragma unroll
-            for (int l = 0; l < 64; ++l) {
+            for (int l = 0; l < CH; ++l) {
                 if (l < n_here) {
-                    const float z1 = bcast(z1l, l), z2 = bcast(z2l, l);
                     StepC<float> c = cst;
-                    if (MODEL != MODEL_STATIC) c = step_coeffs<float>(MODEL, x, (double)(s0 + l) * d.dt, d.dt);
-                    const float vh = __builtin_amdgcn_exp2f(fmaf(bm1, fmaxf(X, xabs), A));
-                    A = fmaf(c.nz, z1, A + c.nd);
-                    const float w2 = fmaf(c.rz, z1, c.rp * z2);
-                    const float Xn = fmaf(vh, fmaf(-hd, vh, w2), X);
-                    X = (Xn < xabs) ? -__builtin_inff() : Xn;
+                    if constexpr (MODEL != MODEL_STATIC) c = step_coeffs_f<MODEL>(xf, (float)(s0 + l) * dtf, sdt, ndt);
+#pragma unroll
+                    for (int q = 0; q < NPATH; ++q) {
+                        const int src = q * LPP + (l >> 1);
+                        const float z1 = bcast((l & 1) ? zo1 : ze1, src), z2 = bcast((l & 1) ? zo2 : ze2, src);
+                        const float vh = __builtin_amdgcn_exp2f(fmaf(bm1, fmaxf(X[q], xabs), A[q]));
+                        A[q] = fmaf(c.nz, z1, A[q] + c.nd);
+                        const float w2 = fmaf(c.rz, z1, c.rp * z2);
+                        const float Xn = fmaf(vh, fmaf(-hd, vh, w2), X[q]);
+                        X[q] = (Xn < xabs) ? -__builtin_inff() : Xn;
+                    }
                     if (s0 + l + 1 == mnext) {
-                        const float F = f0 * __builtin_amdgcn_exp2f(X);
+                        float F[NPATH];
+#pragma unroll
+                        for (int q = 0; q < NPATH; ++q) F[q] = q < n_live ? f0 * __builtin_amdgcn_exp2f(X[q]) : 0.0f;
                         do {
-                            for (int o = offs[mi]; o < offs[mi + 1]; ++o)
-                                acc[o * 64 + lane] += fmaxf(F - Ks[o], 0.0f);
+                            for (int o = offs[mi]; o < offs[mi + 1]; ++o) {
+                                float pay = 0.0f;
+#pragma unroll
+                                for (int q = 0; q < NPATH; ++q) pay += fmaxf(F[q] - Ks[o], 0.0f);
+                                acc[o * 64 + lane] += pay;
+                            }
                             ++mi;
                             mnext = mi < d.n_mat ? mat_steps[mi] : -1;
                         } while (mnext == s0 + l + 1);
@@ -143,20 +196,25 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
         part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = acc[o * 64 + lane];
 }
 
-// Objective of each chain from the partial sums: price_o = disc * S_o / N,
-// f = sum ((target - price) * sw)^2, non-finite prices give +inf.
-__device__ inline void crn_reduce_chain(const McCrnDesc &d, int64_t chain, const double *Y, const float *part,
-                                 const int32_t *obs_row, const double *disc, const double *target,
-                                 const double *sw, double *f, double *model, int write_f) {
-    const int tile = (int)(chain / 64), lane = (int)(chain % 64);
+// Objective of the 64 chains of one tile from the partial sums, by a block of
+// 1024 threads: thread t takes lane t % 64 and the options o = t / 64 (mod
+// 16); price_o = disc * S_o / N, f = sum ((target - price) * sw)^2 with the
+// 16 group sums added in a fixed order; non-finite prices give +inf.
+__device__ inline void crn_reduce_tile(const McCrnDesc &d, int tile, const double *Y, const float *part,
+                                       const int32_t *obs_row, const double *disc, const double *target,
+                                       const double *sw, double *f, double *model, int write_f, double *s_acc,
+                                       int *s_bad) {
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6, ngrp = blockDim.x >> 6;
+    const int64_t chain = (int64_t)tile * 64 + lane;
+    const bool live = chain < d.n_chains;
     double acc = 0.0;
-    bool bad = d.model == MODEL_DYN_II && !case2_feasible(Y + chain * d.np_stride, d.t_max);
+    bool bad = false;
     const double invN = 1.0 / (double)d.n_paths;
-    for (int o = 0; o < d.n_obs; ++o) {
+    for (int o = grp; o < d.n_obs && live; o += ngrp) {
         const float *p = part + (((size_t)tile * d.n_obs + o) * d.n_pblocks) * 64 + lane;
-        double s = 0.0;
-        for (int b = 0; b < d.n_pblocks; ++b) s += (double)p[(size_t)b * 64];
-        const double price = disc[obs_row[o]] * s * invN;
+        double sm = 0.0;
+        for (int b = 0; b < d.n_pblocks; ++b) sm += (double)p[(size_t)b * 64];
+        const double price = disc[obs_row[o]] * sm * invN;
         bad |= !(price > -__builtin_inf() && price < __builtin_inf());
         if (model) model[chain * d.n_obs + o] = price;
         if (target) {
@@ -164,7 +222,18 @@ __device__ inline void crn_reduce_chain(const McCrnDesc &d, int64_t chain, const
             acc = fma(e, e, acc);
         }
     }
-    if (write_f) f[chain] = bad ? __builtin_inf() : acc;
+    s_acc[threadIdx.x] = acc;
+    s_bad[threadIdx.x] = bad ? 1 : 0;
+    __syncthreads();
+    if (grp == 0 && live) {
+        double tot = 0.0;
+        int anybad = d.model == MODEL_DYN_II && !case2_feasible(Y + chain * d.np_stride, d.t_max);
+        for (int g = 0; g < ngrp; ++g) {
+            tot += s_acc[g * 64 + lane];
+            anybad |= s_bad[g * 64 + lane];
+        }
+        if (write_f) f[chain] = anybad ? __builtin_inf() : tot;
+    }
 }
 
 __device__ inline void mc_step_body(const McSaDesc &d, int t, const double *sched_g, const double *sched_h,

@@ -28,6 +28,96 @@ __device__ __forceinline__ bool metropolis(double fy, double fx, double u, doubl
     return delta <= 0.0 || u < exp(-delta / Tk);
 }
 
+// The same decision from the raw random word w (u = (w + 1/2) 2^-32), taken
+// in float wherever the float value of exp(-delta / T) is clearly on one side
+// of u, else by the double test above.  Float error: -delta / T to 3 float
+// roundings, the exponent at most 25 in size, so exp is within 8e-6 relative;
+// the screen's margin is 3e-5, so the result always equals the double test.
+// exp(-25) lies below the smallest uniform 2^-33: larger drops (and +inf or
+// NaN objectives) are rejected outright.
+__device__ __forceinline__ bool metropolis_w(double fy, double fx, uint32_t w, double Tk, float invTf) {
+#pragma clang fp contract(off)
+    const double delta = fy - fx;
+    if (delta <= 0.0) return true;
+    const float a = (float)(-delta) * invTf;
+    if (!(a >= -25.0f)) return false;
+    const float e = __builtin_amdgcn_exp2f(a * 1.44269504088896341f);
+    const float uf = fmaf((float)w, 0x1p-32f, 0x1p-33f);
+    if (uf < e * (1.0f - 3e-5f)) return true;
+    if (uf > e * (1.0f + 3e-5f)) return false;
+    return unit_u32(w) < exp(-delta / Tk);
+}
+
+// Float proposal (float annealing mode): the same reflection and clamp as
+// propose_coord, on the float values the float objective sees.
+__device__ __forceinline__ float propose_coord_f(float x, float u, float h, float lb, float ub) {
+    float y = fmaf(h * fmaf(2.0f, u, -1.0f), ub - lb, x);
+    if (y > ub) y = ub - (y - ub);
+    if (y < lb) y = lb + (lb - y);
+    if (y > ub) y = ub;
+    if (y < lb) y = lb;
+    return y;
+}
+
+// Iterations [t_begin, t_end) of one chain at one temperature level (Section
+// 5): proposal, objective, Metropolis test, best-so-far.  The LPC lanes of a
+// chain draw the Philox blocks of LPC consecutive iterations at once (lane
+// `sub` the blocks of iteration t0 + sub) and hand them round by shuffles,
+// so a lane group draws each block once.  Double mode proposes in double from
+// 32-bit uniforms; float mode proposes in float from 24-bit uniforms.
+template <int NP, int NB, int LPC, typename R, typename FOBJ>
+__device__ __forceinline__ void sa_level(int chain, int sub, int t_begin, int t_end, uint32_t k0, uint32_t k1,
+                                         double h, double Tk, const double *s_lb, const double *s_ub, double *x,
+                                         double &fx, double *bx, double &fb, unsigned long long &nacc, FOBJ f_of) {
+    const float invTf = (float)(1.0 / Tk);
+    const float hf = (float)h;
+    for (int t0 = t_begin; t0 < t_end; t0 += LPC) {
+        uint4 wm[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+            wm[b] = philox4x32_10(make_uint4((uint32_t)chain, (uint32_t)(t0 + sub), (uint32_t)b, 1u), k0, k1);
+        const int kn = min(LPC, t_end - t0);
+#pragma unroll 1
+        for (int k = 0; k < kn; ++k) {
+            uint32_t w[4 * NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                uint4 v = wm[b];
+                if constexpr (LPC > 1) {
+                    v.x = __shfl(v.x, k, LPC);
+                    v.y = __shfl(v.y, k, LPC);
+                    v.z = __shfl(v.z, k, LPC);
+                    v.w = __shfl(v.w, k, LPC);
+                }
+                w[4 * b + 0] = v.x;
+                w[4 * b + 1] = v.y;
+                w[4 * b + 2] = v.z;
+                w[4 * b + 3] = v.w;
+            }
+            double y[NP];
+#pragma unroll
+            for (int c = 0; c < NP; ++c) {
+                if constexpr (sizeof(R) == 4)
+                    y[c] = (double)propose_coord_f((float)x[c], unit_u24f(w[c]), hf, (float)s_lb[c], (float)s_ub[c]);
+                else
+                    y[c] = propose_coord(x[c], unit_u32(w[c]), h, s_lb[c], s_ub[c]);
+            }
+            const double fy = f_of(y);
+            if (metropolis_w(fy, fx, w[NP], Tk, invTf)) {
+#pragma unroll
+                for (int c = 0; c < NP; ++c) x[c] = y[c];
+                fx = fy;
+                ++nacc;
+                if (fy < fb) {
+                    fb = fy;
+#pragma unroll
+                    for (int c = 0; c < NP; ++c) bx[c] = y[c];
+                }
+            }
+        }
+    }
+}
+
 // Wave-level argmin of (f, id): smaller f, ties to the smaller id.
 __device__ __forceinline__ void wave_argmin(double &f, int &id) {
 #pragma unroll

@@ -11,7 +11,13 @@ constexpr int kSlotThreads = 512;   // one workgroup per formula slot
 constexpr int kSlotMaxPts = 1024;
 constexpr int kSlotMaxMat = 32;
 constexpr int kMcPBlocks = 64;      // path blocks of one Monte Carlo slot
-constexpr int kSlotMaxMcObs = 512;  // options of one Monte Carlo slot (LDS: 260 B each)
+constexpr int kSlotMaxMcObs = 600;  // options of one Monte Carlo slot (LDS: 260 B each)
+// Monte Carlo slots are priced by one launch per LDS class, each sized for
+// the largest option count of its class, so that small grids keep several
+// waves per CU: class c holds option counts up to mc_class_obs(c).
+constexpr int kMcClasses = 3;
+__host__ __device__ constexpr int mc_class_obs(int c) { return c == 0 ? 96 : (c == 1 ? 256 : kSlotMaxMcObs); }
+__host__ __device__ inline int mc_slot_class(int n_obs) { return n_obs <= mc_class_obs(0) ? 0 : (n_obs <= mc_class_obs(1) ? 1 : 2); }
 
 // One slot of the serving table (device memory).  Pointers address the
 // request's own region of the server's arena; grid offsets are slot-local.
@@ -53,7 +59,7 @@ struct SlotStatus {
 };
 
 const void *slot_prepare_kernel_ptr();
-const void *sa_slot_kernel_ptr(int kind);
+const void *sa_slot_kernel_ptr();
 const void *mc_slot_crn_kernel_ptr();
 const void *mc_slot_reduce_kernel_ptr();
 const void *mc_slot_step_kernel_ptr();

@@ -126,7 +126,10 @@ struct sabr_server {
     sabr_ctx *ctx = nullptr;
     int device = 0;
     int n_slots = 0, n_mc = 0, Q = 1;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;      // uploads, formula slots, status
+    hipStream_t stream_mc = nullptr;   // Monte Carlo slots (overlap the formula slots)
+    hipEvent_t ev_up = nullptr, ev_mc = nullptr;
+    int mc_iters = 1;                  // Monte Carlo iterations per quantum
     unsigned char *arena_dev = nullptr;
     Arena arena;
     SlotDev *d_slots = nullptr;
@@ -134,8 +137,8 @@ struct sabr_server {
     unsigned char *stage = nullptr;   // pinned upload staging
     size_t stage_bytes = 0, stage_used = 0;
     std::vector<SlotHost> slots;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr, graph_mc = nullptr, graph_st = nullptr;
+    hipGraphExec_t gexec = nullptr, gexec_mc = nullptr, gexec_st = nullptr;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Owned *> queue;
@@ -265,6 +268,7 @@ int upload_slot(sabr_server *s, int si, const Owned &o, size_t base) {
     rq.n_levels = levels;
     rq.n_wg = 1;
     rq.polish = q.sa.polish;
+    rq.rsplit = 1;
     rq.key0 = (uint32_t)(q.sa.seed & 0xffffffffu);
     rq.key1 = (uint32_t)(q.sa.seed >> 32);
     rq.beta = p.beta;
@@ -366,37 +370,75 @@ int clear_slot(sabr_server *s, int si) {
     return stage_copy(s, &s->d_slots[si], &d, sizeof d);
 }
 
-int capture_graph(sabr_server *s) {
-    if (hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return SABR_E_DEVICE;
-    int n = s->n_slots, nmc = s->n_mc, Q = s->Q;
-    SlotDev *ds = s->d_slots;
-    void *a0[] = {&ds, &n};
-    bool ok = hipLaunchKernel(slot_prepare_kernel_ptr(), dim3(n), dim3(256), a0, 0, s->stream) == hipSuccess;
-    void *a1[] = {&ds, &Q};
-    const size_t sm = sa_slot_smem_bytes();
-    ok = ok && hipLaunchKernel(sa_slot_kernel_ptr(KIND_STATIC), dim3(n), dim3(kSlotThreads), a1, sm, s->stream) == hipSuccess;
-    ok = ok && hipLaunchKernel(sa_slot_kernel_ptr(KIND_DYN_I), dim3(n), dim3(kSlotThreads), a1, sm, s->stream) == hipSuccess;
-    if (nmc > 0) {
-        void *a2[] = {&ds};
-        const size_t msm = mc_crn_smem_bytes(kSlotMaxMcObs);
-        ok = ok && hipLaunchKernel(mc_slot_crn_kernel_ptr(), dim3(nmc * kMcPBlocks), dim3(64), a2, msm, s->stream) == hipSuccess;
-        ok = ok && hipLaunchKernel(mc_slot_reduce_kernel_ptr(), dim3(nmc), dim3(64), a2, 0, s->stream) == hipSuccess;
-        ok = ok && hipLaunchKernel(mc_slot_step_kernel_ptr(), dim3(nmc), dim3(256), a2, 0, s->stream) == hipSuccess;
-    }
-    SlotStatus *dst = s->d_status;
-    void *a3[] = {&ds, &n, &dst};
-    ok = ok && hipLaunchKernel(slot_status_kernel_ptr(), dim3((n + 63) / 64), dim3(64), a3, 0, s->stream) == hipSuccess;
-    ok = ok && hipMemcpyAsync(s->h_status, s->d_status, sizeof(SlotStatus) * n, hipMemcpyDeviceToHost, s->stream) == hipSuccess;
-    hipGraph_t g = nullptr;
-    const bool ended = hipStreamEndCapture(s->stream, &g) == hipSuccess;
+// Capture the work queued on `st` by `body` as an executable graph.
+template <typename F>
+int capture_one(hipStream_t st, hipGraph_t *g, hipGraphExec_t *ge, F body) {
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) return SABR_E_DEVICE;
+    const bool ok = body();
+    hipGraph_t gr = nullptr;
+    const bool ended = hipStreamEndCapture(st, &gr) == hipSuccess;
     if (!ok || !ended) {
         hipGetLastError();
-        if (g) hipGraphDestroy(g);
+        if (gr) hipGraphDestroy(gr);
         return SABR_E_DEVICE;
     }
-    s->graph = g;
-    if (hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0) != hipSuccess) return SABR_E_DEVICE;
-    return SABR_OK;
+    *g = gr;
+    return hipGraphInstantiate(ge, gr, nullptr, nullptr, 0) == hipSuccess ? SABR_OK : SABR_E_DEVICE;
+}
+
+// A quantum is three graphs: the formula slots (grid normalisation, then one
+// annealing launch for every static and dynamic slot) on the main stream,
+// the Monte Carlo slots (per iteration: paths for each LDS class, objective,
+// accept/propose) on a second stream so that both run at once, and the
+// status copy once both are done.
+int capture_graph(sabr_server *s) {
+    int n = s->n_slots, nmc = s->n_mc, Q = s->Q, nf = s->n_slots - s->n_mc;
+    SlotDev *ds = s->d_slots;
+    int rc = capture_one(s->stream, &s->graph, &s->gexec, [&] {
+        void *a0[] = {&ds, &n};
+        bool ok = hipLaunchKernel(slot_prepare_kernel_ptr(), dim3(n), dim3(256), a0, 0, s->stream) == hipSuccess;
+        void *a1[] = {&ds, &nmc, &Q};
+        ok = ok && hipLaunchKernel(sa_slot_kernel_ptr(), dim3(nf), dim3(kSlotThreads), a1, sa_slot_smem_bytes(),
+                                   s->stream) == hipSuccess;
+        return ok;
+    });
+    if (rc) return rc;
+    rc = capture_one(s->stream_mc, &s->graph_mc, &s->gexec_mc, [&] {
+        bool ok = true;
+        for (int it = 0; it < s->mc_iters; ++it) {
+            for (int c = 0; c < kMcClasses; ++c) {
+                int cls = c;
+                void *a2[] = {&ds, &cls};
+                ok = ok && hipLaunchKernel(mc_slot_crn_kernel_ptr(), dim3(nmc * kMcPBlocks), dim3(64), a2,
+                                           mc_crn_smem_bytes(mc_class_obs(c)), s->stream_mc) == hipSuccess;
+            }
+            void *a3[] = {&ds};
+            ok = ok && hipLaunchKernel(mc_slot_reduce_kernel_ptr(), dim3(nmc), dim3(1024), a3, 0, s->stream_mc) == hipSuccess;
+            ok = ok && hipLaunchKernel(mc_slot_step_kernel_ptr(), dim3(nmc), dim3(256), a3, 0, s->stream_mc) == hipSuccess;
+        }
+        return ok;
+    });
+    if (rc) return rc;
+    return capture_one(s->stream, &s->graph_st, &s->gexec_st, [&] {
+        SlotStatus *dst = s->d_status;
+        void *a4[] = {&ds, &n, &dst};
+        bool ok = hipLaunchKernel(slot_status_kernel_ptr(), dim3((n + 63) / 64), dim3(64), a4, 0, s->stream) == hipSuccess;
+        ok = ok && hipMemcpyAsync(s->h_status, s->d_status, sizeof(SlotStatus) * n, hipMemcpyDeviceToHost,
+                                  s->stream) == hipSuccess;
+        return ok;
+    });
+}
+
+// One quantum: the Monte Carlo graph waits for this quantum's uploads, runs
+// beside the formula graph, and the status graph waits for both.
+bool run_quantum(sabr_server *s) {
+    return hipEventRecord(s->ev_up, s->stream) == hipSuccess &&
+           hipStreamWaitEvent(s->stream_mc, s->ev_up, 0) == hipSuccess &&
+           hipGraphLaunch(s->gexec_mc, s->stream_mc) == hipSuccess &&
+           hipGraphLaunch(s->gexec, s->stream) == hipSuccess &&
+           hipEventRecord(s->ev_mc, s->stream_mc) == hipSuccess &&
+           hipStreamWaitEvent(s->stream, s->ev_mc, 0) == hipSuccess &&
+           hipGraphLaunch(s->gexec_st, s->stream) == hipSuccess && hipStreamSynchronize(s->stream) == hipSuccess;
 }
 
 void worker_loop(sabr_server *s) {
@@ -460,7 +502,7 @@ void worker_loop(sabr_server *s) {
                 continue;
             }
         }
-        if (hipGraphLaunch(s->gexec, s->stream) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess) {
+        if (!run_quantum(s)) {
             std::lock_guard<std::mutex> lk(s->mu);
             s->device_error = 1;
             s->err = "graph replay failed";
@@ -519,9 +561,13 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
     s->n_slots = max_slots;
     s->n_mc = std::max(1, max_slots / 8);
     s->Q = quantum_levels;
+    s->mc_iters = std::max(1, quantum_levels / 5);
     const size_t budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)1 << 30);
     s->arena.init(budget);
     bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s->stream_mc, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&s->ev_mc, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->arena_dev, budget) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->d_slots, sizeof(SlotDev) * max_slots) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->d_status, sizeof(SlotStatus) * max_slots) == hipSuccess;
@@ -537,8 +583,7 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
     std::memset(z.data(), 0, sizeof(SlotDev) * max_slots);
     ok = hipMemcpy(s->d_slots, z.data(), sizeof(SlotDev) * max_slots, hipMemcpyHostToDevice) == hipSuccess;
     const size_t sm = sa_slot_smem_bytes();
-    ok = ok && hipFuncSetAttribute(sa_slot_kernel_ptr(KIND_STATIC), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) == hipSuccess;
-    ok = ok && hipFuncSetAttribute(sa_slot_kernel_ptr(KIND_DYN_I), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) == hipSuccess;
+    ok = ok && hipFuncSetAttribute(sa_slot_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) == hipSuccess;
     const size_t msm = mc_crn_smem_bytes(kSlotMaxMcObs);
     ok = ok && hipFuncSetAttribute(mc_slot_crn_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)msm) == hipSuccess;
     if (!ok || capture_graph(s) != SABR_OK) {
@@ -657,14 +702,20 @@ int sabr_server_destroy(sabr_server *s) {
     if (s->worker.joinable()) s->worker.join();
     hipSetDevice(s->device);
     if (s->stream) hipStreamSynchronize(s->stream);
-    if (s->gexec) hipGraphExecDestroy(s->gexec);
-    if (s->graph) hipGraphDestroy(s->graph);
+    if (s->stream_mc) hipStreamSynchronize(s->stream_mc);
+    for (hipGraphExec_t ge : {s->gexec, s->gexec_mc, s->gexec_st})
+        if (ge) hipGraphExecDestroy(ge);
+    for (hipGraph_t g : {s->graph, s->graph_mc, s->graph_st})
+        if (g) hipGraphDestroy(g);
+    if (s->ev_up) hipEventDestroy(s->ev_up);
+    if (s->ev_mc) hipEventDestroy(s->ev_mc);
     if (s->arena_dev) hipFree(s->arena_dev);
     if (s->d_slots) hipFree(s->d_slots);
     if (s->d_status) hipFree(s->d_status);
     if (s->h_status) hipHostFree(s->h_status);
     if (s->stage) hipHostFree(s->stage);
     if (s->stream) hipStreamDestroy(s->stream);
+    if (s->stream_mc) hipStreamDestroy(s->stream_mc);
     for (auto *o : s->queue) delete o;
     delete s;
     return SABR_OK;

@@ -384,3 +384,53 @@ def test_sa_mc_objective_trajectory(S, ctx, oracle):
     assert got["n_accept"] == ref["n_accept"]
     np.testing.assert_allclose(got["x"], ref["x"], atol=1e-12)
     assert abs(got["f"] - ref["f"]) <= 1e-3 * ref["f"]
+
+
+def _ctx_with(S, env):
+    """A context created with lane-layout overrides in the environment."""
+    import os
+    old = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        return S.sabr_ctx_create(0)
+    finally:
+        for k, v in old.items():
+            if v is None:
+                del os.environ[k]
+            else:
+                os.environ[k] = v
+
+
+@pytest.mark.parametrize("model", [inputs.DYN_I, inputs.DYN_II])
+def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model):
+    """Float dynamic requests of many chains spread each chain over up to 16
+    lanes (rows and strikes split); only the order of the double partial sums
+    changes, so the accept decisions and the result are those of one lane per
+    chain, for every row split."""
+    if model == inputs.DYN_I:
+        g = inputs.dynamic_surface()
+        xt = g.meta["x_true"]
+    else:
+        g = inputs.make_grid(inputs.dynamic_ladder(10), [np.exp(np.linspace(-0.4, 0.4, 9))] * 10)
+        xt = inputs.dynamic_surface().meta["x_true_case2"]
+    m = omkt(oracle, g)
+    tgt = oracle.model_vols(m, model, xt, 0.7)
+    lb, ub = inputs.box(model)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(model, 0.7, lb, ub),
+                    precision=S.SABR_FP32, n_chains=2048, n_iters=60, seed=0x77)
+    runs = {}
+    for name, env in (("one", {"SABR_LANES_PER_CHAIN": "1"}), ("default", {}),
+                      ("16x16", {"SABR_LANES_PER_CHAIN": "16", "SABR_ROW_SPLIT": "16"}),
+                      ("8x2", {"SABR_LANES_PER_CHAIN": "8", "SABR_ROW_SPLIT": "2"})):
+        c = _ctx_with(S, env) if env else ctx
+        say("wide lanes", model, name)
+        runs[name] = S.sabr_calibrate(c, [req])[0]
+        if env:
+            c.close()
+    base = runs["one"]
+    for name, r in runs.items():
+        say(name, r["x"], r["f"], r["n_accept"])
+        assert r["status"] == 0
+        assert r["n_accept"] == base["n_accept"], name
+        np.testing.assert_allclose(r["x"], base["x"], rtol=0, atol=1e-12)
+        assert r["f"] == pytest.approx(base["f"], rel=1e-12)
