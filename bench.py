@@ -38,6 +38,15 @@ PEAK_VALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 # at quarter rate, the double proposal and the Metropolis test with its
 # double exp and division): ~200 slots.
 SLOTS_PER_PT_EVAL = 39
+# HBM bytes of one sa_kernel launch of this workload, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
+# counter reads for a device copy of 256 MiB (FETCH_SIZE reads 131084 KiB of
+# the 262144 read, WRITE_SIZE exactly 262144): profiles/counters_sa_kernel_static_surface.md.
+# Almost all of it is the level-end exchange between workgroups (candidates
+# written and read across the chip's L2 caches); the grids are read once.
+SA_FETCH_KIB, SA_WRITE_KIB = 792010.375, 154514.3125
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.0144, 1.0
+SA_TRAFFIC_BYTES = (SA_FETCH_KIB * FETCH_SCALE + SA_WRITE_KIB * WRITE_SCALE) * 1024
 SLOTS_SA_PER_ITER = 200
 
 
@@ -297,8 +306,8 @@ def main():
     ap.add_argument("--serve-paths", type=int, default=16384)
     ap.add_argument("--serve-slots", type=int, default=1024)
     ap.add_argument("--serve-quantum", type=int, default=20)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2000)
     ap.add_argument("--no-mc", action="store_true")
@@ -364,11 +373,12 @@ def main():
                                "FP64 sums/decisions/polish",
                    "fits": n_cal, "chains": N_CHAINS, "iterations": N_ITERS, "chain_len": CHAIN_LEN,
                    "points_per_fit": 25},
-        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99))},
+        "latency_ms": {"p50": float(np.percentile(lat_ms, 50)), "p99": float(np.percentile(lat_ms, 99)),
+                       "steps": [round(float(v), 2) for v in lat_ms]},
         "formula_evals_per_s": pt_evals * args.steps / total,
         "max_param_error_vs_truth": param_err,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": SA_TRAFFIC_BYTES,
                      "kernel": kname, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches},
     }
     if not args.no_mc:

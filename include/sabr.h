@@ -159,6 +159,17 @@ int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx 
 void sabr_ctx_destroy(sabr_ctx *ctx);
 /* Text of the last error on this context (never NULL; "" when none). */
 const char *sabr_ctx_last_error(const sabr_ctx *ctx);
+/* Device workspace owned by the caller (for example the memory of a torch
+ * tensor on the context's device): while it is set, the context takes every
+ * device buffer of sabr_calibrate, sabr_objective_batch and sabr_mc_price
+ * from [dev_ptr, dev_ptr + bytes) instead of allocating, starting again at
+ * the beginning on each call, and frees the buffers it had allocated.  A call
+ * that needs more returns SABR_E_BUDGET.  The caller keeps the memory alive
+ * and untouched by other work until the workspace is replaced or the context
+ * destroyed.  dev_ptr NULL returns to the library's own allocations.
+ * Errors: SABR_E_INVAL (not device memory of the context's device, or fewer
+ * than 4096 bytes). */
+int sabr_ctx_set_workspace(sabr_ctx *ctx, void *dev_ptr, size_t bytes);
 /* Timing of the dominant kernel: with enable != 0 the library brackets each
  * launch of its main kernel (annealing, objective or path kernel) with HIP
  * events on the context's stream; sabr_ctx_timing returns the summed event
@@ -200,15 +211,16 @@ int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *
  * I and II, run for many independent requests at once).
  *
  * A worker thread owns a device-resident table of max_slots slots.  A
- * submitted request waits in a FIFO queue until a slot of its kind is free
- * and its device footprint (grid, schedule, chain state, Monte Carlo
- * partials) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each quantum
- * replays captured HIP graphs that normalise new grids, advance every
- * formula slot by quantum_levels temperature levels and, on a second stream
- * at the same time, every Monte Carlo slot by max(1, quantum_levels / 5)
- * iterations, and copy the slot states back; requests admitted while others
- * run join at the next quantum.  Slots 0..max_slots/8-1
- * take Monte Carlo requests, the others formula requests.
+ * submitted request waits in a queue (first come, first served within each
+ * kind) until a slot of its kind is free and its device footprint (grid, schedule, chain state, Monte Carlo
+ * partials) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each formula
+ * quantum replays a captured HIP graph that normalises new grids, advances
+ * every formula slot by quantum_levels temperature levels and copies the
+ * slot states back; beside it, on a second stream, a second captured graph
+ * advances every Monte Carlo slot by one iteration and is relaunched as soon
+ * as it finishes.  Requests admitted while others run join at the next
+ * launch.  Slots 0..max_slots/8-1 take Monte Carlo requests, the others
+ * formula requests.
  *
  * Supported requests: FP32 precision, fixed beta, and either the static
  * Hagan formula (<= 256 chains), the dynamic case I formula (<= 512 chains)
@@ -220,7 +232,7 @@ int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *
  *
  * Thread safety: submit, poll, cancel and stats may be called from any host
  * thread.  The server uses the context only for its device; it owns its own
- * stream and memory.
+ * streams and memory.
  * ------------------------------------------------------------------------- */
 typedef struct sabr_server sabr_server;
 

@@ -116,20 +116,27 @@ __global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, cons
 // Box-Muller for 64 chains.  Payoffs are summed per lane in LDS in float over
 // the paths of the block; partial sums go to device memory lane-contiguous.
 // ---------------------------------------------------------------------------
-template <int MODEL>
+template <int MODEL, int NPATH, bool LDSB>
 __global__ void __launch_bounds__(64) mc_crn_kernel(McCrnDesc d, const double *Y, const int32_t *mat_steps,
                                                    const int32_t *offs, const double *K, float *part) {
     extern __shared__ unsigned char smem[];
-    crn_block<MODEL>(d, blockIdx.x / d.n_pblocks, blockIdx.x % d.n_pblocks, Y, mat_steps, offs, K, part, smem);
+    crn_block<MODEL, NPATH, LDSB>(d, blockIdx.x / d.n_pblocks, blockIdx.x % d.n_pblocks, Y, mat_steps, offs, K,
+                                  part, smem);
 }
 
-__global__ void __launch_bounds__(1024) mc_crn_reduce(McCrnDesc d, const double *Y, const float *part,
-                                                     const int32_t *obs_row, const double *disc,
-                                                     const double *target, const double *sw, double *f,
-                                                     double *model, int write_f) {
-    __shared__ double s_acc[1024];
-    __shared__ int s_bad[1024];
-    crn_reduce_tile(d, blockIdx.x, Y, part, obs_row, disc, target, sw, f, model, write_f, s_acc, s_bad);
+// Model prices and squared errors: grid (tiles, options), 256 threads.
+__global__ void __launch_bounds__(256) mc_crn_prices(McCrnDesc d, const float *part, const int32_t *obs_row,
+                                                    const double *disc, const double *target, const double *sw,
+                                                    double *model, double *e2, int64_t e2_stride) {
+    __shared__ double s_sum[256];
+    crn_price_tile(d, blockIdx.x, blockIdx.y, part, obs_row, disc, target, sw, model, e2, e2_stride, s_sum);
+}
+
+// Objective per chain from the squared errors.
+__global__ void __launch_bounds__(256) mc_crn_objective(McCrnDesc d, const double *Y, const double *e2,
+                                                       int64_t e2_stride, double *f) {
+    const int64_t chain = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (chain < d.n_chains) f[chain] = crn_chain_objective(d, chain, Y, e2, e2_stride);
 }
 
 // ---------------------------------------------------------------------------
@@ -159,15 +166,23 @@ const void *mc_price_kernel_ptr(bool fp32) {
     return fp32 ? (const void *)mc_price_kernel<float> : (const void *)mc_price_kernel<double>;
 }
 const void *mc_price_finalize_ptr() { return (const void *)mc_price_finalize; }
-const void *mc_crn_kernel_ptr(int model) {
-    switch (model) {
-        case MODEL_STATIC: return (const void *)mc_crn_kernel<MODEL_STATIC>;
-        case MODEL_DYN_I: return (const void *)mc_crn_kernel<MODEL_DYN_I>;
-        case MODEL_DYN_II: return (const void *)mc_crn_kernel<MODEL_DYN_II>;
-    }
-    return nullptr;
+// variant: 0 = the production layout (kCrnPaths, kCrnLdsNormals); 1..8 =
+// (1, 2, 4, 8 paths per lane) x (scalar broadcast, LDS broadcast); 9 = 16
+// paths per lane with LDS broadcast; for tuning.
+const void *mc_crn_kernel_ptr(int model, int variant) {
+#define SABR_CRN(MD)                                                                                           \
+    {(const void *)mc_crn_kernel<MD, kCrnPaths, kCrnLdsNormals>, (const void *)mc_crn_kernel<MD, 1, false>,      \
+     (const void *)mc_crn_kernel<MD, 2, false>, (const void *)mc_crn_kernel<MD, 4, false>,                       \
+     (const void *)mc_crn_kernel<MD, 8, false>, (const void *)mc_crn_kernel<MD, 1, true>,                        \
+     (const void *)mc_crn_kernel<MD, 2, true>, (const void *)mc_crn_kernel<MD, 4, true>,                         \
+     (const void *)mc_crn_kernel<MD, 8, true>, (const void *)mc_crn_kernel<MD, 16, true>}
+    static const void *tab[3][10] = {SABR_CRN(MODEL_STATIC), SABR_CRN(MODEL_DYN_I), SABR_CRN(MODEL_DYN_II)};
+#undef SABR_CRN
+    if (model < 0 || model > 2 || variant < 0 || variant > 9) return nullptr;
+    return tab[model][variant];
 }
-const void *mc_crn_reduce_ptr() { return (const void *)mc_crn_reduce; }
+const void *mc_crn_prices_ptr() { return (const void *)mc_crn_prices; }
+const void *mc_crn_objective_ptr() { return (const void *)mc_crn_objective; }
 const void *mc_sa_step_ptr() { return (const void *)mc_sa_step; }
 const void *mc_sa_final_ptr() { return (const void *)mc_sa_final; }
 size_t mc_price_smem_bytes(bool fp32, int m_max, int n_obs) {
@@ -175,6 +190,8 @@ size_t mc_price_smem_bytes(bool fp32, int m_max, int n_obs) {
     const size_t st = (fp32 ? sizeof(StepC<float>) : sizeof(StepC<double>)) * m_max;
     return st + (rs * n_obs + 15) / 16 * 16 + 2 * 4 * sizeof(double) * n_obs;
 }
-size_t mc_crn_smem_bytes(int n_obs) { return sizeof(float) * (((n_obs + 3) / 4) * 4 + 64 * (size_t)n_obs); }
+size_t mc_crn_smem_bytes(int n_obs) {
+    return crn_normals_bytes() + sizeof(float) * (((n_obs + 3) / 4) * 4 + 64 * (size_t)n_obs);
+}
 
 }  // namespace sabr

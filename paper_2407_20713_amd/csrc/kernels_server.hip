@@ -16,9 +16,10 @@ __device__ __forceinline__ PointsD slot_points(const SlotDev &s) {
 }
 __device__ __forceinline__ MatsD slot_mats(const SlotDev &s) { return MatsD{s.T, s.lnf, s.F1, s.offs}; }
 
-// Grid normalisation of newly admitted formula slots (one workgroup per slot).
-__global__ void __launch_bounds__(256) slot_prepare_kernel(SlotDev *slots, int n_slots) {
-    SlotDev &s = slots[blockIdx.x];
+// Grid normalisation of newly admitted formula slots (one workgroup per slot
+// of [first, first + gridDim.x)).
+__global__ void __launch_bounds__(256) slot_prepare_kernel(SlotDev *slots, int first) {
+    SlotDev &s = slots[first + blockIdx.x];
     if (s.state != SLOT_NEW) return;
     if (s.kind != KIND_MC) {
         const ReqDesc &rq = s.rq;
@@ -38,7 +39,6 @@ __global__ void __launch_bounds__(256) slot_prepare_kernel(SlotDev *slots, int n
     }
     __syncthreads();
     if (threadIdx.x == 0) s.state = SLOT_READY;
-    (void)n_slots;
 }
 
 // ---------------------------------------------------------------------------
@@ -217,14 +217,27 @@ __global__ void __launch_bounds__(64) mc_slot_crn_kernel(SlotDev *slots, int cls
     crn_block<MODEL_STATIC>(d, 0, blockIdx.x % kMcPBlocks, s.Y, s.msteps, s.offs, s.K, s.part, smem);
 }
 
-__global__ void __launch_bounds__(1024) mc_slot_reduce_kernel(SlotDev *slots) {
+// Prices and squared errors of the slot's options: block (slot, g) takes the
+// options o = g, g + kMcPriceGroups, ... (four waves split the path blocks).
+__global__ void __launch_bounds__(256) mc_slot_prices_kernel(SlotDev *slots) {
     SlotDev &s = slots[blockIdx.x];
     if (!mc_slot_live(s)) return;
-    __shared__ double s_acc[1024];
-    __shared__ int s_bad[1024];
+    __shared__ double s_sum[256];
     McCrnDesc d = s.crn;
     if (s.iter < 0) d.n_chains = 1;
-    crn_reduce_tile(d, 0, s.Y, s.part, s.obsrow, s.disc, s.target, s.sw, s.fy, nullptr, 1, s_acc, s_bad);
+    for (int o = blockIdx.y; o < d.n_obs; o += kMcPriceGroups) {
+        crn_price_tile(d, 0, o, s.part, s.obsrow, s.disc, s.target, s.sw, nullptr, s.e2, 64, s_sum);
+        __syncthreads();
+    }
+}
+
+// Objective of each chain of the slot (options added in order).
+__global__ void __launch_bounds__(64) mc_slot_objective_kernel(SlotDev *slots) {
+    SlotDev &s = slots[blockIdx.x];
+    if (!mc_slot_live(s)) return;
+    McCrnDesc d = s.crn;
+    if (s.iter < 0) d.n_chains = 1;
+    if (threadIdx.x < d.n_chains) s.fy[threadIdx.x] = crn_chain_objective(d, threadIdx.x, s.Y, s.e2, 64);
 }
 
 __global__ void __launch_bounds__(256) mc_slot_step_kernel(SlotDev *slots) {
@@ -251,9 +264,9 @@ __global__ void __launch_bounds__(256) mc_slot_step_kernel(SlotDev *slots) {
 }
 
 // Status of every slot, for the host (copied back after each quantum).
-__global__ void slot_status_kernel(const SlotDev *slots, int n_slots, SlotStatus *st) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_slots) return;
+__global__ void slot_status_kernel(const SlotDev *slots, int first, int n_slots, SlotStatus *st) {
+    const int i = first + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= first + n_slots) return;
     const SlotDev &s = slots[i];
     SlotStatus o;
     o.state = s.state;
@@ -271,7 +284,8 @@ __global__ void slot_status_kernel(const SlotDev *slots, int n_slots, SlotStatus
 const void *slot_prepare_kernel_ptr() { return (const void *)slot_prepare_kernel; }
 const void *sa_slot_kernel_ptr() { return (const void *)sa_slot_kernel; }
 const void *mc_slot_crn_kernel_ptr() { return (const void *)mc_slot_crn_kernel; }
-const void *mc_slot_reduce_kernel_ptr() { return (const void *)mc_slot_reduce_kernel; }
+const void *mc_slot_prices_kernel_ptr() { return (const void *)mc_slot_prices_kernel; }
+const void *mc_slot_objective_kernel_ptr() { return (const void *)mc_slot_objective_kernel; }
 const void *mc_slot_step_kernel_ptr() { return (const void *)mc_slot_step_kernel; }
 const void *slot_status_kernel_ptr() { return (const void *)slot_status_kernel; }
 size_t sa_slot_smem_bytes() {

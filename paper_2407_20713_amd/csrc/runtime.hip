@@ -23,6 +23,7 @@ namespace {
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = false;   // allocated by the library (else a region of the caller's workspace)
 };
 
 struct EventPair {
@@ -50,6 +51,10 @@ struct sabr_ctx {
     std::vector<EventPair> pool;
     int force_lpc = 0;      // SABR_LANES_PER_CHAIN overrides the choice (1, 2, 4, 8 or 16)
     int force_rsplit = 0;   // SABR_ROW_SPLIT overrides the row split of a lane group (1 .. 16)
+    int crn_variant = 0;    // SABR_CRN_VARIANT: Monte Carlo objective kernel layout (0 = production)
+    // caller's device workspace (sabr_ctx_set_workspace): buffers are carved from it
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0, ws_used = 0;
     // pinned staging for host-to-device copies: valid until the next sync
     unsigned char *stage = nullptr;
     size_t stage_bytes = 0, stage_used = 0;
@@ -77,13 +82,36 @@ enum Slot {
     S_K, S_FWDP, S_BETAP, S_FORMP, S_WGHTP, S_TARGET, S_LFK, S_LKF, S_P1, S_Z, S_Q1, S_Q2, S_SW, S_ROW,
     S_T, S_FWD, S_BETAM, S_LNF, S_F1, S_OFFS, S_REQ, S_WGREQ, S_SCHED_G, S_SCHED_H, S_CAND, S_BAR,
     S_BEST, S_ACC, S_ERR, S_EVALS, S_POLREQ, S_X, S_F, S_MODEL, S_MSTEPS, S_MOFFS, S_DISC, S_OBSROW,
-    S_PART, S_PARTQ, S_PRICE, S_SE, S_Y, S_CX, S_CF, S_BX, S_BF, S_FY, S_MCSTATE, S_NSLOTS
+    S_PART, S_PARTQ, S_E2, S_PRICE, S_SE, S_Y, S_CX, S_CF, S_BX, S_BF, S_FY, S_MCSTATE, S_NSLOTS
 };
+
+// Start of an API call that computes: with a caller workspace, the buffers
+// are carved again from its beginning (the previous call has synchronised).
+void begin_call(sabr_ctx *c) {
+    if (!c->ws) return;
+    for (auto &b : c->bufs) b = DevBuf{};
+    c->ws_used = 0;
+}
 
 int get_buf(sabr_ctx *c, int slot, size_t bytes, void **out) {
     if (bytes == 0) bytes = 16;
     if ((int)c->bufs.size() < S_NSLOTS) c->bufs.resize(S_NSLOTS);
     DevBuf &b = c->bufs[slot];
+    if (c->ws) {
+        // carve from the caller's workspace; a slot keeps its region for the call
+        if (b.bytes < bytes) {
+            const size_t off = (c->ws_used + 255) / 256 * 256;
+            if (off + bytes > c->ws_bytes)
+                return fail(c, SABR_E_BUDGET, "workspace of %zu bytes is too small (needs more than %zu)", c->ws_bytes,
+                            off + bytes);
+            b.p = c->ws + off;
+            b.bytes = bytes;
+            b.owned = false;
+            c->ws_used = off + bytes;
+        }
+        *out = b.p;
+        return SABR_OK;
+    }
     if (b.bytes < bytes) {
         size_t want = std::max(bytes, b.bytes * 3 / 2);
         if (c->budget && c->held - b.bytes + want > c->budget) {
@@ -106,6 +134,7 @@ int get_buf(sabr_ctx *c, int slot, size_t bytes, void **out) {
         }
         b.p = p;
         b.bytes = want;
+        b.owned = true;
         c->held += want;
     }
     *out = b.p;
@@ -459,28 +488,30 @@ struct Group {
 // depends on the other requests of a batch): requests of 1024 chains or more
 // split each chain's work over two lanes, which doubles the waves of the
 // few-but-large requests that would otherwise leave SIMDs half idle.  Float
-// dynamic requests (many maturity rows, each with its own integrals) widen
-// the group up to 16 lanes while the request stays within two waves per SIMD
-// of the whole chip (131072 lanes) and the group within twice its rows.
+// dynamic requests of 256 chains or more (many maturity rows, each with its
+// own integrals, so little work is repeated across the lanes of a group)
+// widen the group up to 16 lanes while the request stays within two waves
+// per SIMD of the whole chip (131072 lanes) and the group within twice its
+// rows.
 int lanes_per_chain(const sabr_ctx *c, const sabr_request &q) {
     const bool wide = wide_lanes_supported(q.problem.model, q.obj.precision == SABR_FP32);
     if (c->force_lpc) return c->force_lpc > 2 && !wide ? 2 : c->force_lpc;
-    if (q.sa.n_chains < 1024) return 1;
-    int lpc = 2;
-    if (wide)
+    if (wide && q.sa.n_chains >= 256) {
+        int lpc = 1;
         while (lpc < 16 && (int64_t)q.sa.n_chains * lpc * 2 <= 131072 && lpc * 2 <= 2 * q.market.n_mat) lpc *= 2;
-    return lpc;
+        return lpc;
+    }
+    return q.sa.n_chains >= 1024 ? 2 : 1;
 }
 
 // Lanes of a group that split the maturity rows (the rest split the strikes of
-// a row): all of them while the rows are at least four per lane, else the
-// largest power of two that leaves four rows per lane.  The static z-form
-// formulas split strikes only.
+// a row): the largest power of two up to the group size that leaves at least
+// two rows per lane.  The static z-form formulas split strikes only.
 int row_split(const sabr_ctx *c, const sabr_request &q, int lpc) {
     if (lpc == 1 || q.problem.model == SABR_STATIC) return 1;
     if (c->force_rsplit) return std::min(c->force_rsplit, lpc);
     int rs = 1;
-    while (rs < lpc && 4 * (rs * 2) <= q.market.n_mat) rs *= 2;
+    while (rs < lpc && 2 * (rs * 2) <= q.market.n_mat) rs *= 2;
     return rs;
 }
 
@@ -488,6 +519,37 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
     const int nr = (int)grp.reqs.size();
     const int lpc = grp.lpc;
     const int chains_per_wg = kWG / lpc;
+    // A request spread over several workgroups needs them all resident at once
+    // (level-end exchange); a batch too large for that runs as consecutive
+    // launches of fewer requests (each request's result is unchanged).
+    if (nr > 1) {
+        const bool fp32 = grp.fp32 != 0;
+        size_t smem = 0;
+        int64_t total = 0;
+        bool multi = false;
+        for (int r : grp.reqs) {
+            const sabr_request &q = reqs[r];
+            smem = std::max(smem, grid_smem_bytes(fp32, q.market.offs[q.market.n_mat], q.market.n_mat));
+            const int64_t nwg = (q.sa.n_chains + chains_per_wg - 1) / chains_per_wg;
+            total += nwg;
+            multi |= nwg > 1;
+        }
+        smem += sa_smem_fixed_bytes();
+        const void *fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0, lpc);
+        int per_cu = 0;
+        if (multi && fn && smem <= c->max_smem) {
+            if (smem > 65536) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWG, smem) != hipSuccess) per_cu = 0;
+            hipGetLastError();
+            if (per_cu > 0 && total > (int64_t)per_cu * c->n_cu) {
+                Group a = grp, b = grp;
+                a.reqs.assign(grp.reqs.begin(), grp.reqs.begin() + nr / 2);
+                b.reqs.assign(grp.reqs.begin() + nr / 2, grp.reqs.end());
+                int rc = run_formula_group(c, reqs, a, out);
+                return rc ? rc : run_formula_group(c, reqs, b, out);
+            }
+        }
+    }
     Packed pk;
     std::vector<ReqDesc> desc(nr);
     std::vector<double> sg, sh;
@@ -687,7 +749,7 @@ int mc_objective_device(sabr_ctx *c, const McGrid &g, int model, int n_par, int 
     void *part;
     int rc;
     if ((rc = get_buf(c, S_PART, sizeof(float) * (size_t)tiles * g.n_obs * d.n_pblocks * 64, &part))) return rc;
-    const void *fn = mc_crn_kernel_ptr(model);
+    const void *fn = mc_crn_kernel_ptr(model, c->crn_variant);
     const size_t smem = mc_crn_smem_bytes(g.n_obs);
     if ((rc = set_smem(c, fn, smem))) return rc;
     const int32_t *ms = g.msteps, *mo = g.moffs;
@@ -697,10 +759,17 @@ int mc_objective_device(sabr_ctx *c, const McGrid &g, int model, int n_par, int 
         return rc;
     const int32_t *orow = g.obsrow;
     const double *disc = g.disc, *tg = g.target, *sw = g.sw;
-    const double *tgp = want_f ? tg : nullptr;
-    int wf = want_f ? 1 : 0;
-    void *a2[] = {&d, &Ydev, &part, &orow, &disc, &tgp, &sw, &fdev, &modeldev, &wf};
-    return launch(c, false, "mc_crn_reduce", mc_crn_reduce_ptr(), dim3((unsigned)tiles), dim3(1024), a2, 0);
+    void *e2 = nullptr;
+    int64_t e2_stride = tiles * 64;
+    if (want_f && (rc = get_buf(c, S_E2, sizeof(double) * (size_t)e2_stride * g.n_obs, &e2))) return rc;
+    void *a2[] = {&d, &part, &orow, &disc, &tg, &sw, &modeldev, &e2, &e2_stride};
+    if ((rc = launch(c, false, "mc_crn_prices", mc_crn_prices_ptr(), dim3((unsigned)tiles, (unsigned)g.n_obs), dim3(256),
+                     a2, 0)))
+        return rc;
+    if (!want_f) return SABR_OK;
+    void *a3[] = {&d, &Ydev, &e2, &e2_stride, &fdev};
+    return launch(c, false, "mc_crn_objective", mc_crn_objective_ptr(), dim3((unsigned)((n_x + 255) / 256)), dim3(256),
+                  a3, 0);
 }
 
 int run_mc_request(sabr_ctx *c, const sabr_request &q, sabr_result &out) {
@@ -813,6 +882,10 @@ int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx 
         const int v = std::atoi(e);
         c->force_lpc = (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) ? v : 0;
     }
+    if (const char *e = std::getenv("SABR_CRN_VARIANT")) {
+        const int v = std::atoi(e);
+        c->crn_variant = (v >= 0 && v <= 9) ? v : 0;
+    }
     if (const char *e = std::getenv("SABR_ROW_SPLIT")) {
         const int v = std::atoi(e);
         c->force_rsplit = (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) ? v : 0;
@@ -838,7 +911,7 @@ void sabr_ctx_destroy(sabr_ctx *c) {
     hipSetDevice(c->device);
     hipStreamSynchronize(c->stream);
     for (auto &b : c->bufs)
-        if (b.p) hipFree(b.p);
+        if (b.p && b.owned) hipFree(b.p);
     for (auto &e : c->pool) {
         hipEventDestroy(e.a);
         hipEventDestroy(e.b);
@@ -853,6 +926,32 @@ void sabr_ctx_destroy(sabr_ctx *c) {
 }
 
 const char *sabr_ctx_last_error(const sabr_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+int sabr_ctx_set_workspace(sabr_ctx *c, void *dev_ptr, size_t bytes) {
+    if (!c) return SABR_E_INVAL;
+    c->err.clear();
+    hipSetDevice(c->device);
+    if (dev_ptr) {
+        hipPointerAttribute_t a;
+        std::memset(&a, 0, sizeof a);
+        if (hipPointerGetAttributes(&a, dev_ptr) != hipSuccess) hipGetLastError();
+        if (a.type != hipMemoryTypeDevice || a.device != c->device)
+            return fail(c, SABR_E_INVAL, "the workspace must be device memory of device %d", c->device);
+        if (bytes < 4096) return fail(c, SABR_E_INVAL, "a workspace needs at least 4096 bytes");
+    }
+    hipStreamSynchronize(c->stream);
+    for (auto &b : c->bufs) {
+        if (b.p && b.owned) {
+            hipFree(b.p);
+            c->held -= b.bytes;
+        }
+        b = DevBuf{};
+    }
+    c->ws = (unsigned char *)dev_ptr;
+    c->ws_bytes = dev_ptr ? bytes : 0;
+    c->ws_used = 0;
+    return SABR_OK;
+}
 
 int sabr_ctx_enable_timing(sabr_ctx *c, int enable) {
     if (!c) return SABR_E_INVAL;
@@ -877,6 +976,7 @@ int sabr_ctx_timing(sabr_ctx *c, int reset, double *kernel_ms, int64_t *launches
 
 int sabr_calibrate(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_result *out) {
     if (!c) return SABR_E_INVAL;
+    begin_call(c);
     if (n_req < 1 || !reqs || !out) return fail(c, SABR_E_INVAL, "need n_req >= 1 and non-NULL arrays");
     c->err.clear();
     hipSetDevice(c->device);
@@ -953,6 +1053,7 @@ int sabr_objective_batch(sabr_ctx *c, const sabr_market *market, const sabr_prob
                          const sabr_objspec *obj, const sabr_mc *mc, int64_t n_x, const double *X, double *f,
                          double *model) {
     if (!c) return SABR_E_INVAL;
+    begin_call(c);
     c->err.clear();
     hipSetDevice(c->device);
     int rc;
@@ -1026,6 +1127,7 @@ int sabr_objective_batch(sabr_ctx *c, const sabr_market *market, const sabr_prob
 int sabr_mc_price(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem, const sabr_mc *mc,
                   int32_t precision, double *price, double *std_err) {
     if (!c) return SABR_E_INVAL;
+    begin_call(c);
     c->err.clear();
     hipSetDevice(c->device);
     int rc;

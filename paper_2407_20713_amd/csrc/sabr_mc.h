@@ -109,12 +109,20 @@ __device__ __forceinline__ StepC<float> step_coeffs_f(const float *xf, float t, 
 // Philox block (path q, step pair j) and turns both of its pairs into
 // normals) and broadcast to all lanes; payoffs go to per-lane float sums in
 // LDS, one per option.
-template <int MODEL, int NPATH = 2>
+// With LDSB the normals of a chunk go through a small LDS table (one
+// broadcast read per step and path) instead of lane reads into scalar
+// registers.
+constexpr int kCrnPaths = 8;        // paths per lane of the production kernels
+constexpr bool kCrnLdsNormals = true;
+__host__ __device__ constexpr int crn_normals_bytes() { return 1024; }   // NPATH x CH float2 = 128 x 8 B (any NPATH)
+
+template <int MODEL, int NPATH = kCrnPaths, bool LDSB = kCrnLdsNormals>
 __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const double *Y, const int32_t *mat_steps,
                           const int32_t *offs, const double *K, float *part, unsigned char *smem) {
     constexpr int LPP = 64 / NPATH;          // lanes per path when drawing normals
     constexpr int CH = 2 * LPP;              // steps per chunk
-    float *Ks = reinterpret_cast<float *>(smem);
+    float2 *ztab = reinterpret_cast<float2 *>(smem);  // [NPATH][CH] normals (LDSB), 1 KB
+    float *Ks = reinterpret_cast<float *>(smem + crn_normals_bytes());
     float *acc = Ks + ((d.n_obs + 3) / 4) * 4;        // [n_obs][64]
     const int lane = threadIdx.x;
     for (int o = lane; o < d.n_obs; o += 64) Ks[o] = (float)K[o];
@@ -156,6 +164,12 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
             float ze1, ze2, zo1, zo2;
             MC<float>::normals(unit_u24f(w.x), unit_u24f(w.y), ze1, ze2);
             MC<float>::normals(unit_u24f(w.z), unit_u24f(w.w), zo1, zo2);
+            if constexpr (LDSB) {
+                __syncthreads();
+                ztab[q_self * CH + 2 * j_self] = make_float2(ze1, ze2);
+                ztab[q_self * CH + 2 * j_self + 1] = make_float2(zo1, zo2);
+                __syncthreads();
+            }
             const int n_here = min(CH, d.m_max - s0);
 #pragma unroll
             for (int l = 0; l < CH; ++l) {
@@ -164,8 +178,16 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
                     if constexpr (MODEL != MODEL_STATIC) c = step_coeffs_f<MODEL>(xf, (float)(s0 + l) * dtf, sdt, ndt);
 #pragma unroll
                     for (int q = 0; q < NPATH; ++q) {
-                        const int src = q * LPP + (l >> 1);
-                        const float z1 = bcast((l & 1) ? zo1 : ze1, src), z2 = bcast((l & 1) ? zo2 : ze2, src);
+                        float z1, z2;
+                        if constexpr (LDSB) {
+                            const float2 z = ztab[q * CH + l];
+                            z1 = z.x;
+                            z2 = z.y;
+                        } else {
+                            const int src = q * LPP + (l >> 1);
+                            z1 = bcast((l & 1) ? zo1 : ze1, src);
+                            z2 = bcast((l & 1) ? zo2 : ze2, src);
+                        }
                         const float vh = __builtin_amdgcn_exp2f(fmaf(bm1, fmaxf(X[q], xabs), A[q]));
                         A[q] = fmaf(c.nz, z1, A[q] + c.nd);
                         const float w2 = fmaf(c.rz, z1, c.rp * z2);
@@ -196,44 +218,42 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
         part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = acc[o * 64 + lane];
 }
 
-// Objective of the 64 chains of one tile from the partial sums, by a block of
-// 1024 threads: thread t takes lane t % 64 and the options o = t / 64 (mod
-// 16); price_o = disc * S_o / N, f = sum ((target - price) * sw)^2 with the
-// 16 group sums added in a fixed order; non-finite prices give +inf.
-__device__ inline void crn_reduce_tile(const McCrnDesc &d, int tile, const double *Y, const float *part,
-                                       const int32_t *obs_row, const double *disc, const double *target,
-                                       const double *sw, double *f, double *model, int write_f, double *s_acc,
-                                       int *s_bad) {
-    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6, ngrp = blockDim.x >> 6;
-    const int64_t chain = (int64_t)tile * 64 + lane;
-    const bool live = chain < d.n_chains;
-    double acc = 0.0;
-    bool bad = false;
-    const double invN = 1.0 / (double)d.n_paths;
-    for (int o = grp; o < d.n_obs && live; o += ngrp) {
-        const float *p = part + (((size_t)tile * d.n_obs + o) * d.n_pblocks) * 64 + lane;
-        double sm = 0.0;
-        for (int b = 0; b < d.n_pblocks; ++b) sm += (double)p[(size_t)b * 64];
-        const double price = disc[obs_row[o]] * sm * invN;
-        bad |= !(price > -__builtin_inf() && price < __builtin_inf());
-        if (model) model[chain * d.n_obs + o] = price;
-        if (target) {
-            const double e = (target[o] - price) * sw[o];
-            acc = fma(e, e, acc);
-        }
-    }
-    s_acc[threadIdx.x] = acc;
-    s_bad[threadIdx.x] = bad ? 1 : 0;
+// Price of option o for the 64 chains of one tile from the path-block
+// partial sums, by a block of 256 threads (four waves): wave w adds the
+// blocks w, w + 4, ... in double, the four wave sums are added in order.
+// price = disc * S / N; e2[o][chain] = ((target - price) sw)^2, +inf for a
+// price that is not finite.
+__device__ inline void crn_price_tile(const McCrnDesc &d, int tile, int o, const float *part, const int32_t *obs_row,
+                                      const double *disc, const double *target, const double *sw, double *model,
+                                      double *e2, int64_t e2_stride, double *s_sum) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const float *p = part + (((size_t)tile * d.n_obs + o) * d.n_pblocks) * 64 + lane;
+    double sm = 0.0;
+    for (int b = w; b < d.n_pblocks; b += nw) sm += (double)p[(size_t)b * 64];
+    s_sum[threadIdx.x] = sm;
     __syncthreads();
-    if (grp == 0 && live) {
-        double tot = 0.0;
-        int anybad = d.model == MODEL_DYN_II && !case2_feasible(Y + chain * d.np_stride, d.t_max);
-        for (int g = 0; g < ngrp; ++g) {
-            tot += s_acc[g * 64 + lane];
-            anybad |= s_bad[g * 64 + lane];
+    const int64_t chain = (int64_t)tile * 64 + lane;
+    if (w == 0 && chain < d.n_chains) {
+        double tot = s_sum[lane];
+        for (int k = 1; k < nw; ++k) tot += s_sum[k * 64 + lane];
+        const double price = disc[obs_row[o]] * tot * (1.0 / (double)d.n_paths);
+        const bool ok = price > -__builtin_inf() && price < __builtin_inf();
+        if (model) model[chain * d.n_obs + o] = price;
+        if (e2) {
+            const double e = (target[o] - price) * sw[o];
+            e2[(int64_t)o * e2_stride + chain] = ok ? e * e : __builtin_inf();
         }
-        if (write_f) f[chain] = anybad ? __builtin_inf() : tot;
     }
+}
+
+// f of one chain: the squared errors added over the options in order; an
+// infeasible case II vector gives +inf.
+__device__ inline double crn_chain_objective(const McCrnDesc &d, int64_t chain, const double *Y, const double *e2,
+                                             int64_t e2_stride) {
+    double f = 0.0;
+    for (int o = 0; o < d.n_obs; ++o) f += e2[(int64_t)o * e2_stride + chain];
+    if (d.model == MODEL_DYN_II && !case2_feasible(Y + chain * d.np_stride, d.t_max)) f = __builtin_inf();
+    return f;
 }
 
 __device__ inline void mc_step_body(const McSaDesc &d, int t, const double *sched_g, const double *sched_h,

@@ -10,7 +10,8 @@ enum SlotKind : int32_t { KIND_STATIC = 0, KIND_DYN_I = 1, KIND_MC = 2 };
 constexpr int kSlotThreads = 512;   // one workgroup per formula slot
 constexpr int kSlotMaxPts = 1024;
 constexpr int kSlotMaxMat = 32;
-constexpr int kMcPBlocks = 64;      // path blocks of one Monte Carlo slot
+constexpr int kMcPBlocks = 128;     // path blocks of one Monte Carlo slot
+constexpr int kMcPriceGroups = 32;  // option groups of the per-slot price launch
 constexpr int kSlotMaxMcObs = 600;  // options of one Monte Carlo slot (LDS: 260 B each)
 // Monte Carlo slots are priced by one launch per LDS class, each sized for
 // the largest option count of its class, so that small grids keep several
@@ -41,6 +42,7 @@ struct SlotDev {
     McSaState *mcst;
     double *Y, *fy;          // [chains * NP], [chains]
     float *part;             // [obs][kMcPBlocks][64]
+    double *e2;              // [obs][64] squared errors
     int32_t *msteps, *obsrow;  // [n_mat], [n_obs]
     int32_t iter;            // next Monte Carlo iteration (-1: initial evaluation pending)
     int32_t pad1;
@@ -61,7 +63,8 @@ struct SlotStatus {
 const void *slot_prepare_kernel_ptr();
 const void *sa_slot_kernel_ptr();
 const void *mc_slot_crn_kernel_ptr();
-const void *mc_slot_reduce_kernel_ptr();
+const void *mc_slot_prices_kernel_ptr();
+const void *mc_slot_objective_kernel_ptr();
 const void *mc_slot_step_kernel_ptr();
 const void *slot_status_kernel_ptr();
 size_t sa_slot_smem_bytes();

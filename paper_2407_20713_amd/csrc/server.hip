@@ -128,8 +128,9 @@ struct sabr_server {
     int n_slots = 0, n_mc = 0, Q = 1;
     hipStream_t stream = nullptr;      // uploads, formula slots, status
     hipStream_t stream_mc = nullptr;   // Monte Carlo slots (overlap the formula slots)
+    hipStream_t stream_cls[kMcClasses] = {};   // fork of the Monte Carlo graph, one per LDS class
     hipEvent_t ev_up = nullptr, ev_mc = nullptr;
-    int mc_iters = 1;                  // Monte Carlo iterations per quantum
+    hipEvent_t ev_fork = nullptr, ev_join[kMcClasses] = {};
     unsigned char *arena_dev = nullptr;
     Arena arena;
     SlotDev *d_slots = nullptr;
@@ -184,6 +185,7 @@ size_t footprint(const sabr_request &q, Layout *lay = nullptr, size_t *offs_out 
         o[k++] = L.take(sizeof(float) * (size_t)n_pts * kMcPBlocks * 64);  // part
         o[k++] = L.take(sizeof(int32_t) * n_mat);                          // msteps
         o[k++] = L.take(sizeof(int32_t) * n_pts);                          // obsrow
+        o[k++] = L.take(sizeof(double) * (size_t)n_pts * 64);              // e2
     }
     if (lay) *lay = L;
     if (offs_out) std::memcpy(offs_out, o, sizeof(size_t) * k);
@@ -309,6 +311,7 @@ int upload_slot(sabr_server *s, int si, const Owned &o, size_t base) {
         d.part = (float *)(b + off[k++]);
         d.msteps = (int32_t *)(b + off[k++]);
         d.obsrow = (int32_t *)(b + off[k++]);
+        d.e2 = (double *)(b + off[k++]);
         std::vector<int32_t> ms(n_mat), orow(n_pts);
         std::vector<double> sw(n_pts);
         int m_max = 0;
@@ -386,66 +389,108 @@ int capture_one(hipStream_t st, hipGraph_t *g, hipGraphExec_t *ge, F body) {
     return hipGraphInstantiate(ge, gr, nullptr, nullptr, 0) == hipSuccess ? SABR_OK : SABR_E_DEVICE;
 }
 
-// A quantum is three graphs: the formula slots (grid normalisation, then one
-// annealing launch for every static and dynamic slot) on the main stream,
-// the Monte Carlo slots (per iteration: paths for each LDS class, objective,
-// accept/propose) on a second stream so that both run at once, and the
-// status copy once both are done.
+// The work is three graphs.  The formula graph (main stream) normalises the
+// grids of new formula slots and advances every formula slot by Q
+// temperature levels in one launch of sa_slot_kernel; the formula status
+// graph copies those slots' states back.  The Monte Carlo graph (second
+// stream) runs one iteration of every Monte Carlo slot (paths for each LDS
+// class, prices, objectives, accept/propose) and copies their states back;
+// it runs beside the formula quanta and is relaunched when it has finished.
 int capture_graph(sabr_server *s) {
-    int n = s->n_slots, nmc = s->n_mc, Q = s->Q, nf = s->n_slots - s->n_mc;
+    int nmc = s->n_mc, nf = s->n_slots - s->n_mc;
+    int Q = s->Q;
     SlotDev *ds = s->d_slots;
     int rc = capture_one(s->stream, &s->graph, &s->gexec, [&] {
-        void *a0[] = {&ds, &n};
-        bool ok = hipLaunchKernel(slot_prepare_kernel_ptr(), dim3(n), dim3(256), a0, 0, s->stream) == hipSuccess;
+        void *a0[] = {&ds, &nmc};
+        bool ok = hipLaunchKernel(slot_prepare_kernel_ptr(), dim3(nf), dim3(256), a0, 0, s->stream) == hipSuccess;
         void *a1[] = {&ds, &nmc, &Q};
         ok = ok && hipLaunchKernel(sa_slot_kernel_ptr(), dim3(nf), dim3(kSlotThreads), a1, sa_slot_smem_bytes(),
                                    s->stream) == hipSuccess;
         return ok;
     });
     if (rc) return rc;
-    rc = capture_one(s->stream_mc, &s->graph_mc, &s->gexec_mc, [&] {
-        bool ok = true;
-        for (int it = 0; it < s->mc_iters; ++it) {
-            for (int c = 0; c < kMcClasses; ++c) {
-                int cls = c;
-                void *a2[] = {&ds, &cls};
-                ok = ok && hipLaunchKernel(mc_slot_crn_kernel_ptr(), dim3(nmc * kMcPBlocks), dim3(64), a2,
-                                           mc_crn_smem_bytes(mc_class_obs(c)), s->stream_mc) == hipSuccess;
-            }
-            void *a3[] = {&ds};
-            ok = ok && hipLaunchKernel(mc_slot_reduce_kernel_ptr(), dim3(nmc), dim3(1024), a3, 0, s->stream_mc) == hipSuccess;
-            ok = ok && hipLaunchKernel(mc_slot_step_kernel_ptr(), dim3(nmc), dim3(256), a3, 0, s->stream_mc) == hipSuccess;
-        }
+    rc = capture_one(s->stream, &s->graph_st, &s->gexec_st, [&] {
+        SlotStatus *dst = s->d_status;
+        void *a4[] = {&ds, &nmc, &nf, &dst};
+        bool ok = hipLaunchKernel(slot_status_kernel_ptr(), dim3((nf + 63) / 64), dim3(64), a4, 0, s->stream) ==
+                  hipSuccess;
+        ok = ok && hipMemcpyAsync(s->h_status + nmc, s->d_status + nmc, sizeof(SlotStatus) * nf,
+                                  hipMemcpyDeviceToHost, s->stream) == hipSuccess;
         return ok;
     });
     if (rc) return rc;
-    return capture_one(s->stream, &s->graph_st, &s->gexec_st, [&] {
+    return capture_one(s->stream_mc, &s->graph_mc, &s->gexec_mc, [&] {
+        // the path launches of the LDS classes are independent branches of the graph
+        bool ok = hipEventRecord(s->ev_fork, s->stream_mc) == hipSuccess;
+        for (int c = 0; c < kMcClasses; ++c) {
+            int cls = c;
+            void *a2[] = {&ds, &cls};
+            ok = ok && hipStreamWaitEvent(s->stream_cls[c], s->ev_fork, 0) == hipSuccess;
+            ok = ok && hipLaunchKernel(mc_slot_crn_kernel_ptr(), dim3(nmc * kMcPBlocks), dim3(64), a2,
+                                       mc_crn_smem_bytes(mc_class_obs(c)), s->stream_cls[c]) == hipSuccess;
+            ok = ok && hipEventRecord(s->ev_join[c], s->stream_cls[c]) == hipSuccess;
+            ok = ok && hipStreamWaitEvent(s->stream_mc, s->ev_join[c], 0) == hipSuccess;
+        }
+        void *a3[] = {&ds};
+        ok = ok && hipLaunchKernel(mc_slot_prices_kernel_ptr(), dim3(nmc, kMcPriceGroups), dim3(256), a3, 0,
+                                   s->stream_mc) == hipSuccess;
+        ok = ok && hipLaunchKernel(mc_slot_objective_kernel_ptr(), dim3(nmc), dim3(64), a3, 0, s->stream_mc) ==
+                   hipSuccess;
+        ok = ok && hipLaunchKernel(mc_slot_step_kernel_ptr(), dim3(nmc), dim3(256), a3, 0, s->stream_mc) == hipSuccess;
+        int zero = 0;
         SlotStatus *dst = s->d_status;
-        void *a4[] = {&ds, &n, &dst};
-        bool ok = hipLaunchKernel(slot_status_kernel_ptr(), dim3((n + 63) / 64), dim3(64), a4, 0, s->stream) == hipSuccess;
-        ok = ok && hipMemcpyAsync(s->h_status, s->d_status, sizeof(SlotStatus) * n, hipMemcpyDeviceToHost,
-                                  s->stream) == hipSuccess;
+        void *a4[] = {&ds, &zero, &nmc, &dst};
+        ok = ok && hipLaunchKernel(slot_status_kernel_ptr(), dim3((nmc + 63) / 64), dim3(64), a4, 0, s->stream_mc) ==
+                   hipSuccess;
+        ok = ok && hipMemcpyAsync(s->h_status, s->d_status, sizeof(SlotStatus) * nmc, hipMemcpyDeviceToHost,
+                                  s->stream_mc) == hipSuccess;
         return ok;
     });
 }
 
-// One quantum: the Monte Carlo graph waits for this quantum's uploads, runs
-// beside the formula graph, and the status graph waits for both.
-bool run_quantum(sabr_server *s) {
-    return hipEventRecord(s->ev_up, s->stream) == hipSuccess &&
-           hipStreamWaitEvent(s->stream_mc, s->ev_up, 0) == hipSuccess &&
-           hipGraphLaunch(s->gexec_mc, s->stream_mc) == hipSuccess &&
-           hipGraphLaunch(s->gexec, s->stream) == hipSuccess &&
-           hipEventRecord(s->ev_mc, s->stream_mc) == hipSuccess &&
-           hipStreamWaitEvent(s->stream, s->ev_mc, 0) == hipSuccess &&
-           hipGraphLaunch(s->gexec_st, s->stream) == hipSuccess && hipStreamSynchronize(s->stream) == hipSuccess;
+// Results of the finished or cancelled slots of [lo, hi) (caller holds the lock).
+void collect(sabr_server *s, int lo, int hi) {
+    const auto now = Clock::now();
+    for (int i = lo; i < hi; ++i) {
+        SlotHost &h = s->slots[i];
+        if (!h.busy) continue;
+        const SlotStatus &st = s->h_status[i];
+        if (st.state != SLOT_DONE && !h.cancel) continue;
+        Done d;
+        d.ticket = h.ticket;
+        std::memset(&d.res, 0, sizeof d.res);
+        if (h.cancel) {
+            d.res.status = SABR_E_CANCELLED;
+            s->cancelled.erase(h.ticket);
+        } else {
+            for (int k = 0; k < h.n_par; ++k) d.res.x[k] = st.x[k];
+            d.res.f = st.f;
+            d.res.f_before_polish = st.f_pre;
+            d.res.n_accept = (int64_t)st.n_accept;
+            d.res.n_evals = (int64_t)st.n_evals;
+            d.res.status = SABR_OK;
+        }
+        d.latency_s = std::chrono::duration<double>(now - h.t_submit).count();
+        s->done.push_back(d);
+        s->arena.release(h.off, h.bytes);
+        h.busy = false;
+        clear_slot(s, i);
+        ++s->completed;
+    }
+}
+
+void device_failed(sabr_server *s, const char *what) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->device_error = 1;
+    s->err = what;
+    s->cv_done.notify_all();
 }
 
 void worker_loop(sabr_server *s) {
     hipSetDevice(s->device);
-    std::vector<int> admitted_now;
+    bool mc_busy = false;   // the Monte Carlo graph is in flight: its slots are not touched
     while (!s->stop.load()) {
-        int active = 0;
+        int active_f = 0, active_mc = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             // cancellations of queued requests
@@ -461,19 +506,32 @@ void worker_loop(sabr_server *s) {
                     ++it;
                 }
             }
-            // admission: FIFO, a request needs a free slot of its kind and room in the arena
-            admitted_now.clear();
-            while (!s->queue.empty()) {
-                Owned *o = s->queue.front();
+            // admission: first come first served within each kind; a request
+            // needs a free slot of its kind and room in the arena (if the arena
+            // is full, nothing behind it is admitted); Monte Carlo slots are
+            // filled only while their graph is idle
+            bool blocked[2] = {false, mc_busy};
+            for (auto it = s->queue.begin(); it != s->queue.end();) {
+                Owned *o = *it;
+                const int kc = o->kind == KIND_MC ? 1 : 0;
+                if (blocked[kc]) {
+                    ++it;
+                    continue;
+                }
                 int si = -1;
-                const int lo = o->kind == KIND_MC ? 0 : s->n_mc, hi = o->kind == KIND_MC ? s->n_mc : s->n_slots;
+                const int lo = kc ? 0 : s->n_mc, hi = kc ? s->n_mc : s->n_slots;
                 for (int i = lo; i < hi; ++i)
                     if (!s->slots[i].busy) {
                         si = i;
                         break;
                     }
+                if (si < 0) {
+                    blocked[kc] = true;
+                    ++it;
+                    continue;
+                }
                 size_t offb = 0;
-                if (si < 0 || !s->arena.alloc(o->bytes, offb)) break;
+                if (!s->arena.alloc(o->bytes, offb)) break;
                 if (upload_slot(s, si, *o, offb) != SABR_OK) {
                     s->device_error = 1;
                     s->arena.release(offb, o->bytes);
@@ -487,57 +545,56 @@ void worker_loop(sabr_server *s) {
                 h.bytes = o->bytes;
                 h.n_par = o->req.problem.n_par;
                 h.cancel = false;
-                s->queue.pop_front();
+                it = s->queue.erase(it);
                 delete o;
                 ++s->admitted;
-                admitted_now.push_back(si);
             }
             for (auto &h : s->slots)
                 if (h.busy && s->cancelled.count(h.ticket)) h.cancel = true;
-            for (auto &h : s->slots) active += h.busy ? 1 : 0;
+            for (int i = 0; i < s->n_slots; ++i)
+                if (s->slots[i].busy) (i < s->n_mc ? active_mc : active_f) += 1;
             s->peak_bytes = std::max(s->peak_bytes, s->arena.in_use());
-            s->peak_active = std::max(s->peak_active, active);
-            if (active == 0) {
+            s->peak_active = std::max(s->peak_active, active_f + active_mc);
+            if (active_f == 0 && active_mc == 0 && !mc_busy) {
                 s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
                 continue;
             }
         }
-        if (!run_quantum(s)) {
-            std::lock_guard<std::mutex> lk(s->mu);
-            s->device_error = 1;
-            s->err = "graph replay failed";
-            s->cv_done.notify_all();
-            return;
+        // a new Monte Carlo iteration once the previous one has finished (it
+        // waits for this round's uploads, which are on the main stream)
+        if (!mc_busy && active_mc > 0) {
+            if (hipEventRecord(s->ev_up, s->stream) != hipSuccess ||
+                hipStreamWaitEvent(s->stream_mc, s->ev_up, 0) != hipSuccess ||
+                hipGraphLaunch(s->gexec_mc, s->stream_mc) != hipSuccess ||
+                hipEventRecord(s->ev_mc, s->stream_mc) != hipSuccess)
+                return device_failed(s, "Monte Carlo graph launch failed");
+            mc_busy = true;
         }
-        s->stage_used = 0;
-        const auto now = Clock::now();
+        if (active_f > 0) {
+            if (hipGraphLaunch(s->gexec, s->stream) != hipSuccess ||
+                hipGraphLaunch(s->gexec_st, s->stream) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
+                return device_failed(s, "formula graph replay failed");
+        } else if (mc_busy) {
+            if (hipEventSynchronize(s->ev_mc) != hipSuccess || hipStreamSynchronize(s->stream) != hipSuccess)
+                return device_failed(s, "Monte Carlo graph failed");
+        }
+        bool mc_done = false;
+        if (mc_busy) {
+            const hipError_t q = hipEventQuery(s->ev_mc);
+            if (q == hipSuccess)
+                mc_done = true;
+            else if (q != hipErrorNotReady)
+                return device_failed(s, "Monte Carlo graph failed");
+            else
+                hipGetLastError();
+        }
+        s->stage_used = 0;   // the main stream has drained: staging is free again
         std::lock_guard<std::mutex> lk(s->mu);
         ++s->quanta;
-        for (int i = 0; i < s->n_slots; ++i) {
-            SlotHost &h = s->slots[i];
-            if (!h.busy) continue;
-            const SlotStatus &st = s->h_status[i];
-            if (st.state != SLOT_DONE && !h.cancel) continue;
-            Done d;
-            d.ticket = h.ticket;
-            std::memset(&d.res, 0, sizeof d.res);
-            if (h.cancel) {
-                d.res.status = SABR_E_CANCELLED;
-                s->cancelled.erase(h.ticket);
-            } else {
-                for (int k = 0; k < h.n_par; ++k) d.res.x[k] = st.x[k];
-                d.res.f = st.f;
-                d.res.f_before_polish = st.f_pre;
-                d.res.n_accept = (int64_t)st.n_accept;
-                d.res.n_evals = (int64_t)st.n_evals;
-                d.res.status = SABR_OK;
-            }
-            d.latency_s = std::chrono::duration<double>(now - h.t_submit).count();
-            s->done.push_back(d);
-            s->arena.release(h.off, h.bytes);
-            h.busy = false;
-            clear_slot(s, i);
-            ++s->completed;
+        if (active_f > 0) collect(s, s->n_mc, s->n_slots);
+        if (mc_done) {
+            collect(s, 0, s->n_mc);
+            mc_busy = false;
         }
         s->cv_done.notify_all();
     }
@@ -561,13 +618,17 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
     s->n_slots = max_slots;
     s->n_mc = std::max(1, max_slots / 8);
     s->Q = quantum_levels;
-    s->mc_iters = std::max(1, quantum_levels / 5);
     const size_t budget = hbm_budget_bytes ? hbm_budget_bytes : ((size_t)1 << 30);
     s->arena.init(budget);
     bool ok = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->stream_mc, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&s->ev_mc, hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess;
+    for (int c = 0; c < kMcClasses; ++c) {
+        ok = ok && hipStreamCreateWithFlags(&s->stream_cls[c], hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&s->ev_join[c], hipEventDisableTiming) == hipSuccess;
+    }
     ok = ok && hipMalloc((void **)&s->arena_dev, budget) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->d_slots, sizeof(SlotDev) * max_slots) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->d_status, sizeof(SlotStatus) * max_slots) == hipSuccess;
@@ -709,6 +770,11 @@ int sabr_server_destroy(sabr_server *s) {
         if (g) hipGraphDestroy(g);
     if (s->ev_up) hipEventDestroy(s->ev_up);
     if (s->ev_mc) hipEventDestroy(s->ev_mc);
+    if (s->ev_fork) hipEventDestroy(s->ev_fork);
+    for (int c = 0; c < kMcClasses; ++c) {
+        if (s->ev_join[c]) hipEventDestroy(s->ev_join[c]);
+        if (s->stream_cls[c]) hipStreamDestroy(s->stream_cls[c]);
+    }
     if (s->arena_dev) hipFree(s->arena_dev);
     if (s->d_slots) hipFree(s->d_slots);
     if (s->d_status) hipFree(s->d_status);

@@ -24,7 +24,8 @@ SABR_OBJ_FORMULA, SABR_OBJ_MC = 0, 1
 SABR_W_ABSOLUTE, SABR_W_RELATIVE = 0, 1
 SABR_FP64, SABR_FP32 = 0, 1
 
-EXPORTED = ["sabr_ctx_create", "sabr_ctx_destroy", "sabr_ctx_last_error", "sabr_ctx_enable_timing",
+EXPORTED = ["sabr_ctx_create", "sabr_ctx_destroy", "sabr_ctx_last_error", "sabr_ctx_set_workspace",
+            "sabr_ctx_enable_timing",
             "sabr_ctx_timing", "sabr_calibrate", "sabr_objective_batch", "sabr_mc_price",
             "sabr_server_create", "sabr_server_submit", "sabr_server_poll", "sabr_server_cancel",
             "sabr_server_stats", "sabr_server_destroy"]
@@ -98,6 +99,7 @@ def lib():
         L.sabr_ctx_destroy.restype = None
         L.sabr_ctx_last_error.argtypes = [C.c_void_p]
         L.sabr_ctx_last_error.restype = C.c_char_p
+        L.sabr_ctx_set_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.sabr_ctx_enable_timing.argtypes = [C.c_void_p, C.c_int]
         L.sabr_ctx_timing.argtypes = [C.c_void_p, C.c_int, _D, C.POINTER(C.c_int64), C.c_char_p, C.c_size_t]
         L.sabr_calibrate.argtypes = [C.c_void_p, C.c_int32, C.POINTER(sabr_request), C.POINTER(sabr_result)]
@@ -202,6 +204,22 @@ def sabr_ctx_destroy(ctx):
 
 def sabr_ctx_last_error(ctx):
     return lib().sabr_ctx_last_error(ctx.h).decode()
+
+
+def sabr_ctx_set_workspace(ctx, buf=None, nbytes=None):
+    """Let the context take its device buffers from `buf` (a CUDA tensor, kept
+    alive by the context handle while set, or a raw device address with
+    nbytes); None returns to the library's own allocations."""
+    if buf is None:
+        ctx.workspace = None
+        return ctx.check(lib().sabr_ctx_set_workspace(ctx.h, None, 0))
+    if hasattr(buf, "data_ptr"):
+        ptr, n = buf.data_ptr(), buf.numel() * buf.element_size()
+    else:
+        ptr, n = int(buf), int(nbytes)
+    rc = ctx.check(lib().sabr_ctx_set_workspace(ctx.h, C.c_void_p(ptr), n if nbytes is None else int(nbytes)))
+    ctx.workspace = buf
+    return rc
 
 
 def sabr_ctx_enable_timing(ctx, enable=True):

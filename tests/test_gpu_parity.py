@@ -401,8 +401,8 @@ def _ctx_with(S, env):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("model", [inputs.DYN_I, inputs.DYN_II])
-def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model):
+@pytest.mark.parametrize("model,n_chains", [(inputs.DYN_I, 2048), (inputs.DYN_II, 2048), (inputs.DYN_I, 300)])
+def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model, n_chains):
     """Float dynamic requests of many chains spread each chain over up to 16
     lanes (rows and strikes split); only the order of the double partial sums
     changes, so the accept decisions and the result are those of one lane per
@@ -417,7 +417,7 @@ def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model):
     tgt = oracle.model_vols(m, model, xt, 0.7)
     lb, ub = inputs.box(model)
     req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(model, 0.7, lb, ub),
-                    precision=S.SABR_FP32, n_chains=2048, n_iters=60, seed=0x77)
+                    precision=S.SABR_FP32, n_chains=n_chains, n_iters=60, seed=0x77)
     runs = {}
     for name, env in (("one", {"SABR_LANES_PER_CHAIN": "1"}), ("default", {}),
                       ("16x16", {"SABR_LANES_PER_CHAIN": "16", "SABR_ROW_SPLIT": "16"}),
@@ -434,3 +434,61 @@ def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model):
         assert r["n_accept"] == base["n_accept"], name
         np.testing.assert_allclose(r["x"], base["x"], rtol=0, atol=1e-12)
         assert r["f"] == pytest.approx(base["f"], rel=1e-12)
+
+
+def test_large_batch_runs_in_resident_parts(S, ctx, oracle):
+    """A batch whose workgroups cannot all be resident at once is run as
+    consecutive launches; every request still gets its own result."""
+    g = inputs.dynamic_surface()
+    m = omkt(oracle, g)
+    lb, ub = inputs.box(inputs.DYN_I)
+    rng = np.random.default_rng(8)
+    reqs = []
+    for k in range(40):
+        xt = lb + (ub - lb) * (0.25 + 0.5 * rng.random(len(lb)))
+        tgt = oracle.model_vols(m, inputs.DYN_I, xt, 0.7)
+        reqs.append(S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_DYN_I, 0.7, lb, ub),
+                              precision=S.SABR_FP32, n_chains=1024, n_iters=20, seed=500 + k))
+    together = S.sabr_calibrate(ctx, reqs)
+    assert all(r["status"] == 0 for r in together)
+    for i in (0, 21, 39):
+        alone = S.sabr_calibrate(ctx, [reqs[i]])[0]
+        assert np.array_equal(alone["x"], together[i]["x"]) and alone["f"] == together[i]["f"]
+        assert alone["n_accept"] == together[i]["n_accept"]
+
+
+def test_caller_workspace_gives_identical_results(S, ctx, oracle):
+    """With a caller-owned device workspace the context allocates nothing and
+    every result is bit-identical to the library-allocated run; a workspace
+    too small for a call is reported as a budget error."""
+    import torch
+    req, m, lb, ub = smile_request(S, oracle, np.array([0.2, -0.3, 0.5]), 1e-4, S.SABR_FP32, 1100, 200, 31,
+                                   polish=True)
+    g = inputs.make_grid([0.25, 0.75], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0)
+    X = random_params(inputs.STATIC, 50, 4)
+    mk = S.Market.from_grid(g, target=np.full(6, 0.2))
+
+    def run(c):
+        r = S.sabr_calibrate(c, [req])[0]
+        f, mod = S.sabr_objective_batch(c, mk, S.Problem(S.SABR_STATIC, 0.7), X, precision=S.SABR_FP32,
+                                        want_model=True)
+        p, se = S.sabr_mc_price(c, S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7, x0=[0.2, -0.3, 0.5]),
+                                4096, 250, 9)
+        return r, f, mod, p, se
+
+    ref = run(ctx)
+    c = S.sabr_ctx_create(0)
+    ws = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    S.sabr_ctx_set_workspace(c, ws)
+    for _ in range(2):
+        got = run(c)
+        assert np.array_equal(got[0]["x"], ref[0]["x"]) and got[0]["f"] == ref[0]["f"]
+        for a, b in zip(got[1:], ref[1:]):
+            assert np.array_equal(a, b)
+    S.sabr_ctx_set_workspace(c, ws, 4096)
+    with pytest.raises(S.SabrError) as e:
+        S.sabr_calibrate(c, [req])
+    assert e.value.code == S.SABR_E_BUDGET
+    S.sabr_ctx_set_workspace(c, None)
+    assert np.array_equal(S.sabr_calibrate(c, [req])[0]["x"], ref[0]["x"])
+    c.close()

@@ -86,7 +86,7 @@ def test_alone_equals_mix_and_quantum(S, ctx, oracle):
     srv.close()
     for kind, t in probe_by_kind.items():
         i = trace.index(t)
-        srv1 = S.Server(ctx, max_slots=8, quantum_levels=11)   # 2 Monte Carlo iterations per quantum
+        srv1 = S.Server(ctx, max_slots=8, quantum_levels=7)
         alone = run_all(srv1, [reqs[i]])[0][0]
         srv1.close()
         a, b = alone, mix[i][0]
