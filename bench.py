@@ -13,6 +13,7 @@ evaluations/s, the annealing kernel's position against the VALU issue peak
 Monte Carlo path-steps/s figure measured apart from the timed step.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -44,8 +45,8 @@ SLOTS_PER_PT_EVAL = 39
 # the 262144 read, WRITE_SIZE exactly 262144): profiles/counters_sa_kernel_static_surface.md.
 # Almost all of it is the level-end exchange between workgroups (candidates
 # written and read across the chip's L2 caches); the grids are read once.
-SA_FETCH_KIB, SA_WRITE_KIB = 792010.375, 154514.3125
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.0144, 1.0
+SA_FETCH_KIB, SA_WRITE_KIB = 790865.9375, 154794.8125
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.2019, 1.0
 SA_TRAFFIC_BYTES = (SA_FETCH_KIB * FETCH_SCALE + SA_WRITE_KIB * WRITE_SCALE) * 1024
 SLOTS_SA_PER_ITER = 200
 
@@ -336,6 +337,11 @@ def main():
         S.sabr_calibrate(ctx, reqs)
     S.sabr_ctx_timing(ctx, reset=True)
     lat = []
+    # Python's cyclic garbage collector is paused over the timed steps (as
+    # timeit does), so that a collection of the interpreter's objects is not
+    # charged to a step
+    gc.collect()
+    gc.disable()
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     results = None
@@ -345,6 +351,7 @@ def main():
         lat.append(time.perf_counter() - t)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_all
+    gc.enable()
     kernel_ms, launches, kname = S.sabr_ctx_timing(ctx, reset=True)
 
     n_cal = len(reqs)

@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(256) objective_kernel(const ReqDesc *rqp, Poin
     extern __shared__ unsigned char smem[];
     const ReqDesc &rq = *rqp;
     Pt<R> *pts = reinterpret_cast<Pt<R> *>(smem);
-    Row<R> *rows = reinterpret_cast<Row<R> *>(smem + sizeof(Pt<R>) * rq.n_pts);
+    Row<R> *rows = reinterpret_cast<Row<R> *>(smem + pts_bytes<R>(rq.n_pts));
     stage_grid<R>(rq, P, Mt, pts, rows);
     __syncthreads();
     constexpr int NP = base_npar<MODEL>() + (BFREE ? 1 : 0);
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
     double *s_lb = reinterpret_cast<double *>(smem + sizeof(ArgminSmem));
     double *s_ub = s_lb + kMaxPar;
     Pt<R> *pts = reinterpret_cast<Pt<R> *>(smem + sizeof(ArgminSmem) + 2 * kMaxPar * sizeof(double));
-    Row<R> *rows = reinterpret_cast<Row<R> *>(reinterpret_cast<unsigned char *>(pts) + sizeof(Pt<R>) * rq.n_pts);
+    Row<R> *rows = reinterpret_cast<Row<R> *>(reinterpret_cast<unsigned char *>(pts) + pts_bytes<R>(rq.n_pts));
     stage_grid<R>(rq, P, Mt, pts, rows);
     if (threadIdx.x < NP) {
         s_lb[threadIdx.x] = rq.lb[threadIdx.x];
@@ -103,10 +103,7 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
     auto f_of = [&](const double *v) {
         double part = objective<MODEL, FORMULA, R, BFREE, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub,
                                                                       rsplit);
-        // butterfly over the lane group: every lane ends with the same bits
-#pragma unroll
-        for (int off = 1; off < LPC; off <<= 1) part = part + __shfl_xor(part, off, 64);
-        return part;
+        return group_sum<LPC>(part);
     };
 
     double x[NP], bx[NP];
@@ -159,7 +156,7 @@ __global__ void __launch_bounds__(64) polish_kernel(const ReqDesc *reqs, const i
     const int req = req_ids[blockIdx.x];
     const ReqDesc &rq = reqs[req];
     Pt<double> *pts = reinterpret_cast<Pt<double> *>(smem);
-    Row<double> *rows = reinterpret_cast<Row<double> *>(smem + sizeof(Pt<double>) * rq.n_pts);
+    Row<double> *rows = reinterpret_cast<Row<double> *>(smem + pts_bytes<double>(rq.n_pts));
     int32_t *prow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(rows) + sizeof(Row<double>) * rq.n_mat);
     stage_grid<double>(rq, P, Mt, pts, rows);
     __syncthreads();
@@ -270,8 +267,8 @@ const void *prepare_points_kernel_ptr() { return (const void *)prepare_points_ke
 const void *prepare_mats_kernel_ptr() { return (const void *)prepare_mats_kernel; }
 
 size_t grid_smem_bytes(bool fp32, int n_pts, int n_mat) {
-    return fp32 ? sizeof(Pt<float>) * n_pts + sizeof(Row<float>) * n_mat
-                : sizeof(Pt<double>) * n_pts + sizeof(Row<double>) * n_mat;
+    return fp32 ? pts_bytes<float>(n_pts) + sizeof(Row<float>) * n_mat
+                : pts_bytes<double>(n_pts) + sizeof(Row<double>) * n_mat;
 }
 size_t sa_smem_fixed_bytes() { return sizeof(ArgminSmem) + 2 * kMaxPar * sizeof(double); }
 

@@ -61,7 +61,7 @@ __device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
     double *s_ub = s_lb + kMaxPar;
     unsigned char *grid = smem + sizeof(ArgminSmem) + 2 * kMaxPar * sizeof(double);
     Pt<float> *pts = reinterpret_cast<Pt<float> *>(grid);
-    Row<float> *rows = reinterpret_cast<Row<float> *>(grid + sizeof(Pt<float>) * rq.n_pts);
+    Row<float> *rows = reinterpret_cast<Row<float> *>(grid + pts_bytes<float>(rq.n_pts));
     const PointsD P = slot_points(s);
     const MatsD Mt = slot_mats(s);
     stage_grid<float>(rq, P, Mt, pts, rows);
@@ -77,7 +77,7 @@ __device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
     const double beta = rq.beta, tmax = rq.t_max;
     auto f_of = [&](const double *v) {
         double part = objective<MODEL, FORMULA, float, false, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub);
-        if constexpr (LPC == 2) part = part + __shfl_xor(part, 1, 64);
+        part = group_sum<LPC>(part);
         return part;
     };
     double x[NP], bx[NP];
@@ -142,46 +142,61 @@ __device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);
     __shared__ unsigned long long s_acc[kSlotThreads / 64];
     if ((threadIdx.x & 63) == 0) s_acc[threadIdx.x >> 6] = a;
-    double xb[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) xb[k] = am.bx[k];
-    const double f_pre = am.bf;
     __syncthreads();
-    // the float grid is no longer needed: stage the double grid for the polish
-    Pt<double> *pd = reinterpret_cast<Pt<double> *>(grid);
-    Row<double> *rd = reinterpret_cast<Row<double> *>(grid + sizeof(Pt<double>) * rq.n_pts);
-    int32_t *prow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(rd) + sizeof(Row<double>) * rq.n_mat);
-    double f_fin = f_pre;
-    unsigned long long ne = 0;
-    if (rq.polish) {
-        stage_grid<double>(rq, P, Mt, pd, rd);
-        __syncthreads();
-        for (int i = 0; i < rq.n_mat; ++i)
-            for (int j = rd[i].p0 + threadIdx.x; j < rd[i].p1; j += blockDim.x) prow[j] = i;
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            double xp[NP];
-#pragma unroll
-            for (int k = 0; k < NP; ++k) xp[k] = xb[k];
-            const double fp = lm_polish<MODEL, FORMULA, false>(xp, pd, rd, prow, rq, &ne);
-            if (fp <= f_pre || !(f_pre < __builtin_inf())) {
-                f_fin = fp;
-#pragma unroll
-                for (int k = 0; k < NP; ++k) xb[k] = xp[k];
-            }
-        }
-    }
     if (threadIdx.x == 0) {
         unsigned long long tot = 0;
         for (int w = 0; w < kSlotThreads / 64; ++w) tot += s_acc[w];
-        s.res_f = f_fin;
-        s.res_f_pre = f_pre;
-        for (int k = 0; k < NP; ++k) s.res_x[k] = xb[k];
+        s.res_f = am.bf;
+        s.res_f_pre = am.bf;
+        for (int k = 0; k < NP; ++k) s.res_x[k] = am.bx[k];
         s.res_accept = tot;
-        s.res_evals = 1 + (unsigned long long)rq.n_chains * (unsigned long long)rq.n_iters + ne;
+        s.res_evals = 1 + (unsigned long long)rq.n_chains * (unsigned long long)rq.n_iters;
         s.level = rq.n_levels;
+        s.state = rq.polish ? SLOT_POLISH : SLOT_DONE;
+    }
+}
+
+// Double-precision Levenberg-Marquardt polish of a finished slot's best state
+// (its own launch: one wave per slot, so that the annealing kernel keeps its
+// registers for the chains).
+template <int KIND>
+__device__ void polish_slot_body(SlotDev &s, unsigned char *smem) {
+    constexpr int MODEL = KIND == KIND_STATIC ? MODEL_STATIC : MODEL_DYN_I;
+    constexpr int NP = base_npar<MODEL>();
+    const ReqDesc &rq = s.rq;
+    Pt<double> *pd = reinterpret_cast<Pt<double> *>(smem);
+    Row<double> *rd = reinterpret_cast<Row<double> *>(smem + pts_bytes<double>(rq.n_pts));
+    int32_t *prow = reinterpret_cast<int32_t *>(reinterpret_cast<unsigned char *>(rd) + sizeof(Row<double>) * rq.n_mat);
+    stage_grid<double>(rq, slot_points(s), slot_mats(s), pd, rd);
+    __syncthreads();
+    for (int i = 0; i < rq.n_mat; ++i)
+        for (int j = rd[i].p0 + threadIdx.x; j < rd[i].p1; j += blockDim.x) prow[j] = i;
+    __syncthreads();
+    double xp[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) xp[k] = s.res_x[k];
+    const double f_pre = s.res_f_pre;
+    unsigned long long ne = 0;
+    const double fp = lm_polish<MODEL, F_HAGAN, false>(xp, pd, rd, prow, rq, &ne);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (fp <= f_pre || !(f_pre < __builtin_inf())) {
+            s.res_f = fp;
+            for (int k = 0; k < NP; ++k) s.res_x[k] = xp[k];
+        }
+        s.res_evals += ne;
         s.state = SLOT_DONE;
     }
+}
+
+__global__ void __launch_bounds__(64) slot_polish_kernel(SlotDev *slots, int first) {
+    SlotDev &s = slots[first + blockIdx.x];
+    if (s.state != SLOT_POLISH) return;
+    extern __shared__ unsigned char smem[];
+    if (s.kind == KIND_STATIC)
+        polish_slot_body<KIND_STATIC>(s, smem);
+    else if (s.kind == KIND_DYN_I)
+        polish_slot_body<KIND_DYN_I>(s, smem);
 }
 
 // One launch for every formula slot (slots [first, first + gridDim.x)): each
@@ -283,15 +298,18 @@ __global__ void slot_status_kernel(const SlotDev *slots, int first, int n_slots,
 
 const void *slot_prepare_kernel_ptr() { return (const void *)slot_prepare_kernel; }
 const void *sa_slot_kernel_ptr() { return (const void *)sa_slot_kernel; }
+const void *slot_polish_kernel_ptr() { return (const void *)slot_polish_kernel; }
 const void *mc_slot_crn_kernel_ptr() { return (const void *)mc_slot_crn_kernel; }
 const void *mc_slot_prices_kernel_ptr() { return (const void *)mc_slot_prices_kernel; }
 const void *mc_slot_objective_kernel_ptr() { return (const void *)mc_slot_objective_kernel; }
 const void *mc_slot_step_kernel_ptr() { return (const void *)mc_slot_step_kernel; }
 const void *slot_status_kernel_ptr() { return (const void *)slot_status_kernel; }
 size_t sa_slot_smem_bytes() {
-    const size_t f32 = sizeof(Pt<float>) * kSlotMaxPts + sizeof(Row<float>) * kSlotMaxMat;
-    const size_t f64 = sizeof(Pt<double>) * kSlotMaxPts + sizeof(Row<double>) * kSlotMaxMat + 4 * kSlotMaxPts;
-    return sizeof(ArgminSmem) + 2 * kMaxPar * sizeof(double) + (f32 > f64 ? f32 : f64);
+    return sizeof(ArgminSmem) + 2 * kMaxPar * sizeof(double) + pts_bytes<float>(kSlotMaxPts) +
+           sizeof(Row<float>) * kSlotMaxMat;
+}
+size_t slot_polish_smem_bytes() {
+    return pts_bytes<double>(kSlotMaxPts) + sizeof(Row<double>) * kSlotMaxMat + sizeof(int32_t) * kSlotMaxPts;
 }
 
 }  // namespace sabr

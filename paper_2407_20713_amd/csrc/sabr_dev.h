@@ -221,23 +221,46 @@ template <> struct CaseI<float> {
     static constexpr int kTerms = 18;
 };
 
+__host__ __device__ constexpr double factorial(int n) {
+    double f = 1.0;
+    for (int m = 2; m <= n; ++m) f *= (double)m;
+    return f;
+}
+__host__ __device__ constexpr double pow2(int n) {
+    double p = 1.0;
+    for (int m = 0; m < n; ++m) p *= 2.0;
+    return p;
+}
+
+// sum_{k < NT} c(k) z^k.  Float: E(z^2) + z O(z^2), two Horner chains of
+// half the depth that the hardware runs side by side.  Double: one Horner
+// chain (the reference evaluation order of the double path).
+template <typename R, int NT, typename C>
+__device__ __forceinline__ R series_even_odd(R z, C c) {
+    if constexpr (sizeof(R) == 8) {
+        R h = 0;
+#pragma unroll
+        for (int k = NT - 1; k >= 0; --k) h = h * z + (R)c(k);
+        return h;
+    } else {
+        const R u = z * z;
+        R e = 0, o = 0;
+#pragma unroll
+        for (int j = (NT - 1) / 2; j >= 0; --j) {
+            if (2 * j + 1 < NT) o = o * u + (R)c(2 * j + 1);
+            e = e * u + (R)c(2 * j);
+        }
+        return e + z * o;
+    }
+}
+
 template <typename R>
 __device__ __forceinline__ void case1_normalised(R y, R x, R &n1, R &n2, R &e1, R &e2) {
     constexpr int NT = CaseI<R>::kTerms;
     if (fabs((double)y) < CaseI<R>::kSwitch) {
-        R h1 = 0, h2 = 0;
-        double fk = 1.0;   // (NT+2)! built down by division below
-        // coefficients c_k = 6/(k+3)! and 6(k+1)/(k+3)!, evaluated from the top
-#pragma unroll
-        for (int k = NT - 1; k >= 0; --k) {
-            double f = 1.0;
-            for (int m = 2; m <= k + 3; ++m) f *= (double)m;
-            h1 = h1 * (-y) + (R)(6.0 / f);
-            h2 = h2 * (-y) + (R)(6.0 * (k + 1) / f);
-        }
-        (void)fk;
-        n1 = h1;
-        n2 = h2;
+        // c_k = 6/(k+3)! and 6(k+1)/(k+3)!
+        n1 = series_even_odd<R, NT>(-y, [](int k) { return 6.0 / factorial(k + 3); });
+        n2 = series_even_odd<R, NT>(-y, [](int k) { return 6.0 * (k + 1) / factorial(k + 3); });
     } else {
         const R ey = M<R>::ex(-y);
         const R c = (R)6 * M<R>::rcp(y * y * y);
@@ -245,18 +268,9 @@ __device__ __forceinline__ void case1_normalised(R y, R x, R &n1, R &n2, R &e1, 
         n2 = c * ((R)2 * (ey - (R)1) + y * (ey + (R)1));
     }
     if (fabs((double)x) < CaseI<R>::kSwitch) {
-        R g1 = 0, g2 = 0;
-#pragma unroll
-        for (int k = NT - 1; k >= 0; --k) {
-            double f2 = 1.0, f4 = 1.0, p2 = 1.0;
-            for (int m = 2; m <= k + 2; ++m) f2 *= (double)m;
-            for (int m = 2; m <= k + 4; ++m) f4 *= (double)m;
-            for (int m = 0; m < k + 4; ++m) p2 *= 2.0;
-            g1 = g1 * (-x) + (R)(2.0 / f2);
-            g2 = g2 * (-x) + (R)(3.0 * (p2 - 8.0) / f4);
-        }
-        e1 = g1;
-        e2 = g2;
+        // c_k = 2/(k+2)! and 3 (2^(k+4) - 8)/(k+4)!
+        e1 = series_even_odd<R, NT>(-x, [](int k) { return 2.0 / factorial(k + 2); });
+        e2 = series_even_odd<R, NT>(-x, [](int k) { return 3.0 * (pow2(k + 4) - 8.0) / factorial(k + 4); });
     } else {
         const R ex = M<R>::ex(-x);
         const R ix2 = M<R>::rcp(x * x);

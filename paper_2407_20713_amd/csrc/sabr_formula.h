@@ -18,6 +18,13 @@ struct alignas(16) Row {
     R T, lnf, F1, pad;    // maturity, ln f, f^(1-beta) (beta fixed)
     int32_t p0, p1, q0, q1;
 };
+// The point records are followed by kPtPad spare records, so that the point
+// loops can read ahead past a row's end (the values read there are unused).
+constexpr int kPtPad = 8;
+template <typename R>
+__host__ __device__ constexpr size_t pts_bytes(int n_pts) {
+    return sizeof(Pt<R>) * (size_t)(n_pts + kPtPad);
+}
 
 template <int MODEL>
 constexpr int base_npar() { return MODEL == MODEL_STATIC ? 3 : (MODEL == MODEL_DYN_I ? 5 : 9); }
@@ -255,39 +262,45 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
         // that their dependency chains interleave, the next pair's LDS records
         // requested before the current pair is computed, and one branch per
         // pair into the double near-the-money series.
+        const float c1a2 = ev.c1a2, c2rna = ev.c2rna, c3n2 = ev.c3n2, noa = ev.noa, alf = ev.al;
+        auto pair = [&](const Pt<R> &pa, const Pt<R> &pb) {
+            const float za = noa * pa.Z, zb = noa * pb.Z;
+            float zxa = za * __builtin_amdgcn_rcpf(x_log_f32(za, ev.rh, ev.lr1, ev.lr2));
+            float zxb = zb * __builtin_amdgcn_rcpf(x_log_f32(zb, ev.rh, ev.lr1, ev.lr2));
+            const bool ia = fabsf(za) < (float)kZIsland, ib = fabsf(zb) < (float)kZIsland;
+            if (__builtin_expect(ia || ib, 0)) {
+                if (ia) zxa = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)za));
+                if (ib) zxb = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)zb));
+            }
+            const float ca = fmaf(fmaf(c1a2, pa.Q2, fmaf(c2rna, pa.Q1, c3n2)), pa.T, 1.0f);
+            const float cb = fmaf(fmaf(c1a2, pb.Q2, fmaf(c2rna, pb.Q1, c3n2)), pb.T, 1.0f);
+            const float sa = alf * pa.P1 * zxa * ca, sb = alf * pb.P1 * zxb * cb;
+            bad |= !vol_ok(sa) || !vol_ok(sb);
+            const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
+            acc = fma(ea, ea, acc);
+            acc = fma(eb, eb, acc);
+        };
+        auto single = [&](const Pt<R> &p) {
+            const float sig = ev.point(p);
+            bad |= !vol_ok(sig);
+            const double e = fma(-(double)sig, p.sw, p.tsw);
+            acc = fma(e, e, acc);
+        };
         for (int i = 0; i < n_mat; ++i) {
             const Row<R> rw = rows[i];
-            const float c1a2 = ev.c1a2, c2rna = ev.c2rna, c3n2 = ev.c3n2, noa = ev.noa, alf = ev.al;
             int j = rw.p0 + sub;
             if (j >= rw.p1) continue;
-            Pt<R> na = pts[j], nb = pts[min(j + LPC, rw.p1 - 1)];
-            for (; j + LPC < rw.p1; j += 2 * LPC) {
+            // records loaded one pair ahead; reads past the row's end land in
+            // the next row or the spare records and are not used
+            const Pt<R> *pp = pts + j;
+            Pt<R> na = pp[0], nb = pp[LPC];
+            for (; j + LPC < rw.p1; j += 2 * LPC, pp += 2 * LPC) {
                 const Pt<R> pa = na, pb = nb;
-                na = pts[min(j + 2 * LPC, rw.p1 - 1)];
-                nb = pts[min(j + 3 * LPC, rw.p1 - 1)];
-                const float za = noa * pa.Z, zb = noa * pb.Z;
-                float zxa = za * __builtin_amdgcn_rcpf(x_log_f32(za, ev.rh, ev.lr1, ev.lr2));
-                float zxb = zb * __builtin_amdgcn_rcpf(x_log_f32(zb, ev.rh, ev.lr1, ev.lr2));
-                const bool ia = fabsf(za) < (float)kZIsland, ib = fabsf(zb) < (float)kZIsland;
-                if (__builtin_expect(ia || ib, 0)) {
-                    if (ia) zxa = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)za));
-                    if (ib) zxb = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)zb));
-                }
-                const float ca = fmaf(fmaf(c1a2, pa.Q2, fmaf(c2rna, pa.Q1, c3n2)), pa.T, 1.0f);
-                const float cb = fmaf(fmaf(c1a2, pb.Q2, fmaf(c2rna, pb.Q1, c3n2)), pb.T, 1.0f);
-                const float sa = alf * pa.P1 * zxa * ca, sb = alf * pb.P1 * zxb * cb;
-                bad |= !vol_ok(sa) || !vol_ok(sb);
-                const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
-                acc = fma(ea, ea, acc);
-                acc = fma(eb, eb, acc);
+                na = pp[2 * LPC];
+                nb = pp[3 * LPC];
+                pair(pa, pb);
             }
-            if (j < rw.p1) {
-                const Pt<R> p = na;
-                const float sig = ev.point(p);
-                bad |= !vol_ok(sig);
-                const double e = fma(-(double)sig, p.sw, p.tsw);
-                acc = fma(e, e, acc);
-            }
+            if (j < rw.p1) single(na);
         }
         return bad ? __builtin_inf() : acc;
     }

@@ -112,7 +112,7 @@ __device__ __forceinline__ StepC<float> step_coeffs_f(const float *xf, float t, 
 // With LDSB the normals of a chunk go through a small LDS table (one
 // broadcast read per step and path) instead of lane reads into scalar
 // registers.
-constexpr int kCrnPaths = 8;        // paths per lane of the production kernels
+constexpr int kCrnPaths = 16;       // paths per lane of the production kernels
 constexpr bool kCrnLdsNormals = true;
 __host__ __device__ constexpr int crn_normals_bytes() { return 1024; }   // NPATH x CH float2 = 128 x 8 B (any NPATH)
 
@@ -150,10 +150,13 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
     const int64_t p_end = min<int64_t>(p_begin + d.paths_per_block, d.n_paths);
     for (int64_t path = p_begin; path < p_end; path += NPATH) {
         const int n_live = (int)min<int64_t>(NPATH, p_end - path);
-        float X[NPATH], A[NPATH];
+        // X: log2(F/f0), -inf once absorbed; Xc: X clamped at the absorption
+        // level (what the local volatility sees, finite)
+        float X[NPATH], Xc[NPATH], A[NPATH];
 #pragma unroll
         for (int q = 0; q < NPATH; ++q) {
             X[q] = 0.0f;
+            Xc[q] = 0.0f;
             A[q] = A0;
         }
         int mi = 0;
@@ -166,8 +169,8 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
             MC<float>::normals(unit_u24f(w.z), unit_u24f(w.w), zo1, zo2);
             if constexpr (LDSB) {
                 __syncthreads();
-                ztab[q_self * CH + 2 * j_self] = make_float2(ze1, ze2);
-                ztab[q_self * CH + 2 * j_self + 1] = make_float2(zo1, zo2);
+                ztab[(2 * j_self) * NPATH + q_self] = make_float2(ze1, ze2);
+                ztab[(2 * j_self + 1) * NPATH + q_self] = make_float2(zo1, zo2);
                 __syncthreads();
             }
             const int n_here = min(CH, d.m_max - s0);
@@ -176,23 +179,27 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
                 if (l < n_here) {
                     StepC<float> c = cst;
                     if constexpr (MODEL != MODEL_STATIC) c = step_coeffs_f<MODEL>(xf, (float)(s0 + l) * dtf, sdt, ndt);
+                    // the step's normals of all paths first (one LDS wait per step)
+                    float2 zz[NPATH];
 #pragma unroll
                     for (int q = 0; q < NPATH; ++q) {
-                        float z1, z2;
                         if constexpr (LDSB) {
-                            const float2 z = ztab[q * CH + l];
-                            z1 = z.x;
-                            z2 = z.y;
+                            zz[q] = ztab[l * NPATH + q];
                         } else {
                             const int src = q * LPP + (l >> 1);
-                            z1 = bcast((l & 1) ? zo1 : ze1, src);
-                            z2 = bcast((l & 1) ? zo2 : ze2, src);
+                            zz[q] = make_float2(bcast((l & 1) ? zo1 : ze1, src), bcast((l & 1) ? zo2 : ze2, src));
                         }
-                        const float vh = __builtin_amdgcn_exp2f(fmaf(bm1, fmaxf(X[q], xabs), A[q]));
+                    }
+#pragma unroll
+                    for (int q = 0; q < NPATH; ++q) {
+                        const float z1 = zz[q].x, z2 = zz[q].y;
+                        const float vh = __builtin_amdgcn_exp2f(fmaf(bm1, Xc[q], A[q]));
                         A[q] = fmaf(c.nz, z1, A[q] + c.nd);
                         const float w2 = fmaf(c.rz, z1, c.rp * z2);
                         const float Xn = fmaf(vh, fmaf(-hd, vh, w2), X[q]);
-                        X[q] = (Xn < xabs) ? -__builtin_inff() : Xn;
+                        const bool absorbed = Xn < xabs;
+                        X[q] = absorbed ? -__builtin_inff() : Xn;
+                        Xc[q] = absorbed ? xabs : Xn;
                     }
                     if (s0 + l + 1 == mnext) {
                         float F[NPATH];

@@ -59,6 +59,28 @@ __device__ __forceinline__ float propose_coord_f(float x, float u, float h, floa
     return y;
 }
 
+// Sum of a double over the LPC consecutive lanes of a lane group (LPC <= 16),
+// with DPP lane moves: swaps inside quads (lane ^ 1, lane ^ 2), then the
+// mirror inside each 8 and each 16 lanes.  Each step adds a value and its
+// partner's in opposite orders on the two lanes of a pair, so every lane of
+// the group ends with the same bits.
+template <int DPP>
+__device__ __forceinline__ double dpp_move(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), DPP, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), DPP, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <int LPC>
+__device__ __forceinline__ double group_sum(double v) {
+    if constexpr (LPC >= 2) v = v + dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    if constexpr (LPC >= 4) v = v + dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    if constexpr (LPC >= 8) v = v + dpp_move<0x141>(v);   // row_half_mirror
+    if constexpr (LPC >= 16) v = v + dpp_move<0x140>(v);  // row_mirror
+    static_assert(LPC <= 16, "lane groups of at most 16 lanes");
+    return v;
+}
+
 // Iterations [t_begin, t_end) of one chain at one temperature level (Section
 // 5): proposal, objective, Metropolis test, best-so-far.  The LPC lanes of a
 // chain draw the Philox blocks of LPC consecutive iterations at once (lane
@@ -77,23 +99,25 @@ __device__ __forceinline__ void sa_level(int chain, int sub, int t_begin, int t_
         for (int b = 0; b < NB; ++b)
             wm[b] = philox4x32_10(make_uint4((uint32_t)chain, (uint32_t)(t0 + sub), (uint32_t)b, 1u), k0, k1);
         const int kn = min(LPC, t_end - t0);
+        // the NP + 1 words of iteration t0 + k come from lane k of the group;
+        // the next iteration's are fetched before this one's objective
+        constexpr int NW = NP + 1;
+        auto fetch = [&](int k, uint32_t *w) {
+#pragma unroll
+            for (int i = 0; i < NW; ++i) {
+                const uint4 &v = wm[i / 4];
+                const uint32_t word = (i % 4 == 0) ? v.x : (i % 4 == 1) ? v.y : (i % 4 == 2) ? v.z : v.w;
+                if constexpr (LPC > 1)
+                    w[i] = __shfl(word, k, LPC);
+                else
+                    w[i] = word;
+            }
+        };
+        uint32_t w[NW], wn[NW];
+        fetch(0, w);
 #pragma unroll 1
         for (int k = 0; k < kn; ++k) {
-            uint32_t w[4 * NB];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                uint4 v = wm[b];
-                if constexpr (LPC > 1) {
-                    v.x = __shfl(v.x, k, LPC);
-                    v.y = __shfl(v.y, k, LPC);
-                    v.z = __shfl(v.z, k, LPC);
-                    v.w = __shfl(v.w, k, LPC);
-                }
-                w[4 * b + 0] = v.x;
-                w[4 * b + 1] = v.y;
-                w[4 * b + 2] = v.z;
-                w[4 * b + 3] = v.w;
-            }
+            if (k + 1 < kn) fetch(k + 1, wn);
             double y[NP];
 #pragma unroll
             for (int c = 0; c < NP; ++c) {
@@ -114,6 +138,8 @@ __device__ __forceinline__ void sa_level(int chain, int sub, int t_begin, int t_
                     for (int c = 0; c < NP; ++c) bx[c] = y[c];
                 }
             }
+#pragma unroll
+            for (int i = 0; i < NW; ++i) w[i] = wn[i];
         }
     }
 }

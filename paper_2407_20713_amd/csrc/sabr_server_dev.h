@@ -4,7 +4,7 @@
 
 namespace sabr {
 
-enum SlotState : int32_t { SLOT_FREE = 0, SLOT_NEW = 1, SLOT_READY = 2, SLOT_RUNNING = 3, SLOT_DONE = 4 };
+enum SlotState : int32_t { SLOT_FREE = 0, SLOT_NEW = 1, SLOT_READY = 2, SLOT_RUNNING = 3, SLOT_DONE = 4, SLOT_POLISH = 5 };
 enum SlotKind : int32_t { KIND_STATIC = 0, KIND_DYN_I = 1, KIND_MC = 2 };
 
 constexpr int kSlotThreads = 512;   // one workgroup per formula slot
@@ -68,5 +68,7 @@ const void *mc_slot_objective_kernel_ptr();
 const void *mc_slot_step_kernel_ptr();
 const void *slot_status_kernel_ptr();
 size_t sa_slot_smem_bytes();
+size_t slot_polish_smem_bytes();
+const void *slot_polish_kernel_ptr();
 
 }  // namespace sabr

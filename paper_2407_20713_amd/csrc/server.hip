@@ -406,6 +406,8 @@ int capture_graph(sabr_server *s) {
         void *a1[] = {&ds, &nmc, &Q};
         ok = ok && hipLaunchKernel(sa_slot_kernel_ptr(), dim3(nf), dim3(kSlotThreads), a1, sa_slot_smem_bytes(),
                                    s->stream) == hipSuccess;
+        ok = ok && hipLaunchKernel(slot_polish_kernel_ptr(), dim3(nf), dim3(64), a0, slot_polish_smem_bytes(),
+                                   s->stream) == hipSuccess;
         return ok;
     });
     if (rc) return rc;
@@ -645,6 +647,8 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
     ok = hipMemcpy(s->d_slots, z.data(), sizeof(SlotDev) * max_slots, hipMemcpyHostToDevice) == hipSuccess;
     const size_t sm = sa_slot_smem_bytes();
     ok = ok && hipFuncSetAttribute(sa_slot_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) == hipSuccess;
+    ok = ok && hipFuncSetAttribute(slot_polish_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)slot_polish_smem_bytes()) == hipSuccess;
     const size_t msm = mc_crn_smem_bytes(kSlotMaxMcObs);
     ok = ok && hipFuncSetAttribute(mc_slot_crn_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)msm) == hipSuccess;
     if (!ok || capture_graph(s) != SABR_OK) {
