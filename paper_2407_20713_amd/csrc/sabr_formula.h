@@ -306,10 +306,27 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
     }
     const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
     const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
+    // float: two points per step with their own partial sums (two independent
+    // dependency chains), added once at the end; double: one sum in point order
+    constexpr bool kTwo = sizeof(R) == 4;
+    double acc2 = 0.0;
     for (int i = rsub; i < n_mat; i += RS) {
         const Row<R> rw = rows[i];
         ev.row(rw);
-        for (int j = rw.p0 + psub; j < rw.p1; j += PS) {
+        int j = rw.p0 + psub;
+        for (; kTwo && j + PS < rw.p1; j += 2 * PS) {
+            const Pt<R> pa = pts[j], pb = pts[j + PS];
+            const R sa = ev.point(pa), sb = ev.point(pb);
+            bad |= !vol_ok(sa) || !vol_ok(sb);
+            const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
+            acc = fma(ea, ea, acc);
+            acc2 = fma(eb, eb, acc2);
+            if (WRITE) {
+                out[j] = (double)sa;
+                out[j + PS] = (double)sb;
+            }
+        }
+        for (; j < rw.p1; j += PS) {
             const Pt<R> p = pts[j];
             const R sig = ev.point(p);
             bad |= !vol_ok(sig);
@@ -318,6 +335,7 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
             if (WRITE) out[j] = (double)sig;
         }
     }
+    if constexpr (kTwo) acc = acc + acc2;
     return bad ? __builtin_inf() : acc;
 }
 
