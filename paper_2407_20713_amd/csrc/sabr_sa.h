@@ -144,17 +144,25 @@ __device__ __forceinline__ void sa_level(int chain, int sub, int t_begin, int t_
     }
 }
 
-// Wave-level argmin of (f, id): smaller f, ties to the smaller id.
-__device__ __forceinline__ void wave_argmin(double &f, int &id) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double fo = __shfl_xor(f, off, 64);
-        const int io = __shfl_xor(id, off, 64);
-        if (fo < f || (fo == f && io < id)) {
-            f = fo;
-            id = io;
-        }
+// Wave-level argmin of (f, id): smaller f, ties to the smaller id (a total
+// order, so any pairing of the lanes gives the same winner).  Inside each 16
+// lanes by DPP moves (quad swaps, half-row and row mirrors), across the rows
+// by two lane shuffles.  Every lane of the wave takes part.
+template <int DPP>
+__device__ __forceinline__ int dpp_move_i(int v) { return __builtin_amdgcn_mov_dpp(v, DPP, 0xf, 0xf, false); }
+__device__ __forceinline__ void argmin_step(double &f, int &id, double fo, int io) {
+    if (fo < f || (fo == f && io < id)) {
+        f = fo;
+        id = io;
     }
+}
+__device__ __forceinline__ void wave_argmin(double &f, int &id) {
+    argmin_step(f, id, dpp_move<0xB1>(f), dpp_move_i<0xB1>(id));
+    argmin_step(f, id, dpp_move<0x4E>(f), dpp_move_i<0x4E>(id));
+    argmin_step(f, id, dpp_move<0x141>(f), dpp_move_i<0x141>(id));
+    argmin_step(f, id, dpp_move<0x140>(f), dpp_move_i<0x140>(id));
+    argmin_step(f, id, __shfl_xor(f, 16, 64), __shfl_xor(id, 16, 64));
+    argmin_step(f, id, __shfl_xor(f, 32, 64), __shfl_xor(id, 32, 64));
 }
 
 struct ArgminSmem {
@@ -221,29 +229,36 @@ __device__ inline void request_argmin(double f, int chain, bool active, const do
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         __syncthreads();
-        // the first wave reads every candidate at once and takes their argmin
+        // the first wave reads every candidate (with its x) at once and takes
+        // their argmin; the winning lane hands its x over
         if (threadIdx.x < 64) {
             double cf = __builtin_inf();
-            int cid = 0x7fffffff, cw = 0;
+            int cid = 0x7fffffff;
+            double cx[NP];
+#pragma unroll
+            for (int k = 0; k < NP; ++k) cx[k] = 0.0;
             for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
                 const double fw = __hip_atomic_load(&half[w].f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const int iw = __hip_atomic_load(&half[w].chain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                double xw[NP];
+#pragma unroll
+                for (int k = 0; k < NP; ++k)
+                    xw[k] = __hip_atomic_load(&half[w].x[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (fw < cf || (fw == cf && iw < cid)) {
                     cf = fw;
                     cid = iw;
-                    cw = w;
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) cx[k] = xw[k];
                 }
             }
             int key = cid;
             double kf = cf;
             wave_argmin(kf, key);
-            // the lane holding the winning chain id names its workgroup
             const unsigned long long m = __ballot(cid == key && cf == kf);
             const int src = __ffsll((long long)m) - 1;
-            const int bw = __shfl(cw, src, 64);
-            if (threadIdx.x < NP)
-                s.bx[threadIdx.x] = __hip_atomic_load(&half[bw].x[threadIdx.x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (threadIdx.x == 0) {
+            if (threadIdx.x == src) {
+#pragma unroll
+                for (int k = 0; k < NP; ++k) s.bx[k] = cx[k];
                 s.bf = kf;
                 s.bid = key;
             }
