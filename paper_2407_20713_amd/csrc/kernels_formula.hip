@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(256) objective_kernel(const ReqDesc *rqp, Poin
 template <int MODEL, int FORMULA, typename R, bool BFREE, int LPC>
 __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const int32_t *wg_req,
                                                  PointsD P, MatsD Mt, const double *sched_g,
-                                                 const double *sched_h, Cand *cands, uint32_t *bar,
+                                                 const double *sched_h, Cand *cands,
                                                  ChainOut *best_out, unsigned long long *accepts,
                                                  int32_t *err) {
     constexpr int NP = base_npar<MODEL>() + (BFREE ? 1 : 0);
@@ -121,14 +121,14 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
         const double Tk = T0 * g;
         const int t1 = min((lev + 1) * L, n_iters);
         if (active) sa_level<NP, NB, LPC, R>(chain, sub, lev * L, t1, k0, k1, h, Tk, s_lb, s_ub, x, fx, bx, fb, nacc, f_of);
-        request_argmin<NP>(fx, chain, active, x, am, rq, wg_local, round++, cands, bar, req, err);
+        request_argmin<NP>(fx, chain, active, x, am, rq, wg_local, round++, cands, err);
         fx = am.bf;
 #pragma unroll
         for (int k = 0; k < NP; ++k) x[k] = am.bx[k];
         __syncthreads();
     }
     // best-so-far over all chains of the request
-    request_argmin<NP>(fb, chain, active, bx, am, rq, wg_local, round++, cands, bar, req, err);
+    request_argmin<NP>(fb, chain, active, bx, am, rq, wg_local, round++, cands, err);
     // accepted moves: workgroup sum, one integer atomic per workgroup
     unsigned long long a = (active && sub == 0) ? nacc : 0ull;
 #pragma unroll

@@ -110,7 +110,7 @@ __device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
         if (active)
             sa_level<NP, NB, LPC, float>(chain, sub, lev * L, t1, rq.key0, rq.key1, h, Tk, s_lb, s_ub, x, fx, bx, fb,
                                          nacc, f_of);
-        request_argmin<NP>(fx, chain, active, x, am, rq, 0, 0, nullptr, nullptr, 0, nullptr);
+        request_argmin<NP>(fx, chain, active, x, am, rq, 0, 0, nullptr, nullptr);
         fx = am.bf;
 #pragma unroll
         for (int k = 0; k < NP; ++k) x[k] = am.bx[k];
@@ -136,7 +136,7 @@ __device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
         return;
     }
     // finished: best over the chains, accepted moves, polish
-    request_argmin<NP>(fb, chain, active, bx, am, rq, 0, 0, nullptr, nullptr, 0, nullptr);
+    request_argmin<NP>(fb, chain, active, bx, am, rq, 0, 0, nullptr, nullptr);
     unsigned long long a = (active && sub == 0) ? nacc : 0ull;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off, 64);

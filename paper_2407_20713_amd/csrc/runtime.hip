@@ -80,7 +80,7 @@ using namespace sabrhost;
 // Slots of the context's reusable device buffers.
 enum Slot {
     S_K, S_FWDP, S_BETAP, S_FORMP, S_WGHTP, S_TARGET, S_LFK, S_LKF, S_P1, S_Z, S_Q1, S_Q2, S_SW, S_ROW,
-    S_T, S_FWD, S_BETAM, S_LNF, S_F1, S_OFFS, S_REQ, S_WGREQ, S_SCHED_G, S_SCHED_H, S_CAND, S_BAR,
+    S_T, S_FWD, S_BETAM, S_LNF, S_F1, S_OFFS, S_REQ, S_WGREQ, S_SCHED_G, S_SCHED_H, S_CAND,
     S_BEST, S_ACC, S_ERR, S_EVALS, S_POLREQ, S_X, S_F, S_MODEL, S_MSTEPS, S_MOFFS, S_DISC, S_OBSROW,
     S_PART, S_PARTQ, S_E2, S_PRICE, S_SE, S_Y, S_CX, S_CF, S_BX, S_BF, S_FY, S_MCSTATE, S_NSLOTS
 };
@@ -593,15 +593,14 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
     if ((rc = upload(c, S_REQ, desc, &dreq)) || (rc = upload(c, S_WGREQ, wg_req, &dwg)) ||
         (rc = upload(c, S_SCHED_G, sg, &dsg)) || (rc = upload(c, S_SCHED_H, sh, &dsh)))
         return rc;
-    void *cand, *bar, *best, *acc, *err, *evals;
+    void *cand, *best, *acc, *err, *evals;
     if ((rc = get_buf(c, S_CAND, sizeof(Cand) * std::max(cand_slots, 1), &cand)) ||
-        (rc = get_buf(c, S_BAR, sizeof(uint32_t) * kBarStride * nr, &bar)) ||
         (rc = get_buf(c, S_BEST, sizeof(ChainOut) * nr, &best)) ||
         (rc = get_buf(c, S_ACC, sizeof(unsigned long long) * nr, &acc)) ||
         (rc = get_buf(c, S_ERR, sizeof(int32_t), &err)) ||
         (rc = get_buf(c, S_EVALS, sizeof(unsigned long long) * nr, &evals)))
         return rc;
-    HIPCHK(c, hipMemsetAsync(bar, 0, sizeof(uint32_t) * kBarStride * nr, c->stream));
+    HIPCHK(c, hipMemsetAsync(cand, 0, sizeof(Cand) * std::max(cand_slots, 1), c->stream));   // exchange tags
     HIPCHK(c, hipMemsetAsync(acc, 0, sizeof(unsigned long long) * nr, c->stream));
     HIPCHK(c, hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
     HIPCHK(c, hipMemsetAsync(evals, 0, sizeof(unsigned long long) * nr, c->stream));
@@ -626,7 +625,7 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
     }
     PointsD P = g.P;
     MatsD Mt = g.Mt;
-    void *args[] = {&dreq, &dwg, &P, &Mt, &dsg, &dsh, &cand, &bar, &best, &acc, &err};
+    void *args[] = {&dreq, &dwg, &P, &Mt, &dsg, &dsh, &cand, &best, &acc, &err};
     if ((rc = launch(c, true, "sa_kernel", fn, dim3(n_blocks), dim3(kWG), args, smem, multi_wg))) return rc;
 
     std::vector<ChainOut> hpre(nr);

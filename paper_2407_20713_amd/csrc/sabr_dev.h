@@ -76,10 +76,9 @@ struct ChainOut {
 struct alignas(128) Cand {   // level-end candidate of one workgroup (own cache line)
     double f;
     int32_t chain;
-    int32_t pad;
+    uint32_t tag;            // exchange round + 1 once f, chain and x are published
     double x[kMaxPar];
 };
-constexpr int kBarStride = 64;   // uint32 words between the barrier counters of two requests
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10, from its published definition (Salmon et al., SC'11).

@@ -175,14 +175,16 @@ struct ArgminSmem {
 };
 
 // Level-end argmin over every chain of the request (workgroups of one request
-// exchange candidates through device memory and a counter).  Afterwards every
-// thread sees the winner in s.bf / s.bx.  `round` counts exchanges; slots
-// alternate between two halves so that a fast workgroup can never overwrite
-// a slot another one has not read yet.
+// exchange candidates through device memory).  Afterwards every thread sees
+// the winner in s.bf / s.bx.  `round` counts exchanges; slots alternate
+// between two halves so that a fast workgroup can never overwrite a slot
+// another one has not read yet.  Each workgroup publishes its candidate with
+// a release store of the round's tag; the first wave of every workgroup
+// watches all the request's slots (lane w slot w) until their tags show the
+// round, then takes an acquire fence and reads them.
 template <int NP>
 __device__ inline void request_argmin(double f, int chain, bool active, const double *x, ArgminSmem &s,
-                               const ReqDesc &rq, int wg_local, int round, Cand *cands, uint32_t *bar,
-                               int req, int32_t *err) {
+                               const ReqDesc &rq, int wg_local, int round, Cand *cands, int32_t *err) {
     double wf = active ? f : __builtin_inf();
     int wid = active ? chain : 0x7fffffff;
     wave_argmin(wf, wid);
@@ -211,24 +213,27 @@ __device__ inline void request_argmin(double f, int chain, bool active, const do
     __syncthreads();
     if (rq.n_wg > 1) {
         Cand *half = cands + rq.cand_off + (round & 1) * rq.n_wg;
+        const uint32_t tag = (uint32_t)round + 1u;
         if (threadIdx.x == 0) {
             Cand &c = half[wg_local];
             c.f = s.bf;
             c.chain = s.bid;
             for (int k = 0; k < NP; ++k) c.x[k] = s.bx[k];
-            __hip_atomic_fetch_add(&bar[req * kBarStride], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const uint32_t want = (uint32_t)(round + 1) * (uint32_t)rq.n_wg;
-            int spins = 0;
-            while (__hip_atomic_load(&bar[req * kBarStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < want) {
-                __builtin_amdgcn_s_sleep(1);
-                if (++spins > (1 << 24)) {
-                    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    break;
+            __hip_atomic_store(&c.tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (threadIdx.x < 64) {
+            for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
+                int spins = 0;
+                while (__hip_atomic_load(&half[w].tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > (1 << 24)) {
+                        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
                 }
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __syncthreads();
         // the first wave reads every candidate (with its x) at once and takes
         // their argmin; the winning lane hands its x over
         if (threadIdx.x < 64) {
