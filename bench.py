@@ -43,10 +43,10 @@ SLOTS_PER_PT_EVAL = 39
 # FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
 # counter reads for a device copy of 256 MiB (FETCH_SIZE reads 131084 KiB of
 # the 262144 read, WRITE_SIZE exactly 262144): profiles/counters_sa_kernel_static_surface.md.
-# Almost all of it is the level-end exchange between workgroups (candidates
-# written and read across the chip's L2 caches); the grids are read once.
-SA_FETCH_KIB, SA_WRITE_KIB = 790865.9375, 154794.8125
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.2019, 1.0
+# Almost all of it is the level-end exchange between workgroups (candidate
+# slots written and watched across the chip's L2 caches); the grids are read once.
+SA_FETCH_KIB, SA_WRITE_KIB = 1109916.0, 154906.28125
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.2067, 1.0
 SA_TRAFFIC_BYTES = (SA_FETCH_KIB * FETCH_SCALE + SA_WRITE_KIB * WRITE_SCALE) * 1024
 SLOTS_SA_PER_ITER = 200
 
