@@ -149,3 +149,34 @@ def test_cancel_timeout_and_rejection(S, ctx, oracle):
         srv.submit(bad)
     assert e.value.code == S.SABR_E_INVAL
     srv.close()
+
+
+def test_monte_carlo_lds_classes_alone_equals_mix(S, ctx, oracle):
+    """Monte Carlo requests in each LDS class of the serving loop (up to 96,
+    256 and 600 options) give bitwise the same result alone and together
+    (for two quantum lengths)."""
+    reqs = []
+    for k, (n_mat, n_k) in enumerate(((4, 15), (8, 25), (12, 41))):
+        T = [0.25 * (i + 1) for i in range(n_mat)]
+        g = inputs.make_grid(T, [np.exp(np.linspace(-0.3, 0.3, n_k))] * n_mat, f0=1.0)
+        m = oracle.Market(g.T, g.fwd, g.offs, g.K, disc=g.disc)
+        tgt, _ = oracle.mc_prices(m, oracle.STATIC, [0.25, -0.2, 0.4], 0.7, 256, 50, 900 + k)
+        tgt = np.maximum(tgt, 1e-6)
+        lb, ub = inputs.box(inputs.STATIC)
+        reqs.append(S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                              kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32,
+                              n_chains=24, n_iters=6, seed=40 + k, n_paths=300, steps_per_year=50,
+                              mc_seed=70 + k))
+        say("class case", k, "options", g.n_obs)
+    srv = S.Server(ctx, max_slots=16, quantum_levels=3)
+    mix = run_all(srv, reqs)
+    srv.close()
+    for i, r in enumerate(reqs):
+        srv1 = S.Server(ctx, max_slots=16, quantum_levels=5)
+        alone = run_all(srv1, [r])[0][0]
+        srv1.close()
+        a, b = alone, mix[i][0]
+        say("mc class", i, a["x"][:3], a["f"], b["f"])
+        assert a["status"] == 0 and b["status"] == 0
+        assert np.array_equal(a["x"], b["x"]) and a["f"] == b["f"] and a["n_accept"] == b["n_accept"]
+        assert np.isfinite(a["f"]) and a["f"] >= 0.0
