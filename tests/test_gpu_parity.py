@@ -492,3 +492,23 @@ def test_caller_workspace_gives_identical_results(S, ctx, oracle):
     S.sabr_ctx_set_workspace(c, None)
     assert np.array_equal(S.sabr_calibrate(c, [req])[0]["x"], ref[0]["x"])
     c.close()
+
+
+def test_mc_objective_calibration_recovers_truth(S, ctx):
+    """Monte Carlo objective calibration with targets priced on the same
+    common paths at the true parameters (so the truth is an exact minimum)
+    recovers them to 1e-3."""
+    g = inputs.make_grid([0.5, 1.0], [np.exp(np.linspace(-0.25, 0.25, 5))] * 2, f0=1.0)
+    xt = np.array([0.25, -0.3, 0.45])
+    lb, ub = inputs.box(inputs.STATIC)
+    _, tgt = S.sabr_objective_batch(ctx, S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7), xt[None, :],
+                                    kind=S.SABR_OBJ_MC, precision=S.SABR_FP32, n_paths=2048, steps_per_year=50,
+                                    mc_seed=11, want_model=True)
+    req = S.Request(S.Market.from_grid(g, target=tgt[0]), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=256,
+                    n_iters=150, seed=5, n_paths=2048, steps_per_year=50, mc_seed=11)
+    r = S.sabr_calibrate(ctx, [req])[0]
+    say("mc recovery", r["x"][:3], r["f"])
+    assert r["status"] == 0
+    np.testing.assert_allclose(r["x"][:3], xt, atol=1e-3)
+    assert r["f"] < 1e-6
