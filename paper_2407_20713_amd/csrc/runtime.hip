@@ -606,6 +606,13 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
     HIPCHK(c, hipMemsetAsync(evals, 0, sizeof(unsigned long long) * nr, c->stream));
 
     const bool fp32 = grp.fp32 != 0;
+    // the polish stages the double grid: refuse a grid it cannot hold before annealing
+    for (int r = 0; r < nr; ++r) {
+        const size_t psm = grid_smem_bytes(false, desc[r].n_pts, desc[r].n_mat) + sizeof(int32_t) * desc[r].n_pts;
+        if (desc[r].polish && psm > c->max_smem)
+            return fail(c, SABR_E_INVAL, "the polish needs %zu bytes of LDS for this grid, the device has %zu", psm,
+                        c->max_smem);
+    }
     size_t smem = 0;
     for (int r = 0; r < nr; ++r) smem = std::max(smem, grid_smem_bytes(fp32, desc[r].n_pts, desc[r].n_mat));
     smem += sa_smem_fixed_bytes();

@@ -512,3 +512,58 @@ def test_mc_objective_calibration_recovers_truth(S, ctx):
     assert r["status"] == 0
     np.testing.assert_allclose(r["x"][:3], xt, atol=1e-3)
     assert r["f"] < 1e-6
+
+
+@pytest.mark.parametrize("n_chains,n_iters,chain_len,n_strikes", [
+    (1, 1, 10, 15),      # one chain, one iteration
+    (3, 7, 10, 15),      # a single, partial temperature level
+    (65, 23, 4, 15),     # two waves of chains, ragged last level
+    (300, 40, 10, 1),    # one strike
+])
+def test_sa_degenerate_sizes_follow_oracle(S, ctx, oracle, n_chains, n_iters, chain_len, n_strikes):
+    """Degenerate annealing sizes (one chain, one iteration, a partial last
+    level, a one-point grid) take the oracle's decisions in FP64."""
+    g = inputs.single_smile() if n_strikes > 1 else inputs.make_grid([1.0], [[1.1]], f0=1.0)
+    m = omkt(oracle, g)
+    tgt = oracle.model_vols(m, oracle.STATIC, [0.2, -0.3, 0.5], 0.7)
+    m.target = tgt
+    lb, ub = inputs.box(inputs.STATIC)
+    cooling = 0.99 ** (1000.0 / n_iters)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    precision=S.SABR_FP64, n_chains=n_chains, n_iters=n_iters, chain_len=chain_len,
+                    cooling=cooling, seed=0x77 + n_chains)
+    got = S.sabr_calibrate(ctx, [req])[0]
+    ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, n_chains, n_iters, 0x77 + n_chains,
+                           chain_len=chain_len, cooling=cooling)
+    say("degenerate", n_chains, n_iters, chain_len, n_strikes, got["n_accept"], ref["n_accept"])
+    assert got["n_accept"] == ref["n_accept"]
+    np.testing.assert_allclose(got["x"], ref["x"], rtol=0, atol=1e-12)
+
+
+def test_grid_too_large_for_lds_is_rejected(S, ctx):
+    """A grid whose records do not fit the LDS of a workgroup is refused with
+    SABR_E_INVAL before anything runs."""
+    T = [0.5 + 0.01 * i for i in range(40)]
+    g = inputs.make_grid(T, [np.exp(np.linspace(-0.5, 0.5, 100))] * 40, f0=1.0)   # 4000 points
+    lb, ub = inputs.box(inputs.STATIC)
+    req = S.Request(S.Market.from_grid(g, target=np.full(g.n_obs, 0.2)), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    precision=S.SABR_FP64, n_chains=64, n_iters=10)
+    with pytest.raises(S.SabrError) as e:
+        S.sabr_calibrate(ctx, [req])
+    assert e.value.code == S.SABR_E_INVAL
+
+
+def test_polish_grid_too_large_is_rejected_before_annealing(S, ctx):
+    """A float grid that fits the annealing kernel but not the double polish
+    is refused up front when the polish is requested, and runs without it."""
+    T = [0.5 + 0.01 * i for i in range(25)]
+    g = inputs.make_grid(T, [np.exp(np.linspace(-0.5, 0.5, 100))] * 25, f0=1.0)   # 2500 points
+    lb, ub = inputs.box(inputs.STATIC)
+    mk = S.Market.from_grid(g, target=np.full(g.n_obs, 0.2))
+    with pytest.raises(S.SabrError) as e:
+        S.sabr_calibrate(ctx, [S.Request(mk, S.Problem(S.SABR_STATIC, 0.7, lb, ub), precision=S.SABR_FP32,
+                                         n_chains=64, n_iters=10, polish=True)])
+    assert e.value.code == S.SABR_E_INVAL
+    r = S.sabr_calibrate(ctx, [S.Request(mk, S.Problem(S.SABR_STATIC, 0.7, lb, ub), precision=S.SABR_FP32,
+                                         n_chains=64, n_iters=10, polish=False)])[0]
+    assert r["status"] == 0 and np.isfinite(r["f"])
