@@ -144,7 +144,10 @@ struct ModelEval {
     R noa, c1a2, c2rna, c3n2, lr1, lr2, d1, d2;   // z-form static formulas
     R F1;                                         // f^(1-beta) of the current row
     Quad<R> q;                                    // expansion / dynamic row block
-    XzSeries<8> xs;                               // near-the-money x(z)/z (float bulk)
+    // near-the-money x(z)/z (float bulk): |z| < 0.05 and |P_n(rho)| <= 1, so
+    // six terms leave a truncation below 0.05^6 / 7 = 2.3e-9, under the float
+    // rounding of the result
+    XzSeries<6> xs;
     const double *y;
 
     // Returns false for a case II vector outside rho(t) in [-1,1], nu(t) > 0.
@@ -158,7 +161,10 @@ struct ModelEval {
         beta = (R)beta_d;
         omb = (R)(1.0 - beta_d);
         if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION) {
-            noa = nu / al;
+            if constexpr (sizeof(R) == 4)
+                noa = nu * M<R>::rcp(al);   // hardware reciprocal (1 ulp) in the float bulk
+            else
+                noa = nu / al;
             c1a2 = omb * omb * (R)(1.0 / 24.0) * al * al;
             c2rna = beta * (R)0.25 * rh * nu * al;
             c3n2 = ((R)2 - (R)3 * rh * rh) * (R)(1.0 / 24.0) * nu * nu;
