@@ -186,6 +186,29 @@ int sabr_ctx_timing(sabr_ctx *ctx, int reset, double *kernel_ms, int64_t *launch
  * then returns SABR_E_INVAL without running anything). */
 int sabr_calibrate(sabr_ctx *ctx, int32_t n_req, const sabr_request *reqs, sabr_result *out);
 
+/* Prepared batches (Section 5, Technique I): the same calibration as
+ * sabr_calibrate for formula-objective requests, split into a setup call
+ * that validates the requests, packs their grids, schedules and launch plan
+ * and copies them to device memory, and a run call that works only on that
+ * device-resident data (grid normalisation, annealing, polish) and copies
+ * back the results.  Repeated runs repeat the calibration: a run returns
+ * bit for bit what sabr_calibrate returns for the same requests.
+ *   sabr_batch_prepare: the requests are read during the call only (the
+ *     caller may free them on return).  The batch owns its device memory
+ *     (not taken from the context's budget or workspace) until
+ *     sabr_batch_destroy, and must be destroyed before its context.
+ *     Errors: SABR_E_INVAL (a request fails validation, or uses the Monte
+ *     Carlo objective), SABR_E_BUDGET, SABR_E_NOMEM, SABR_E_DEVICE.
+ *   sabr_batch_run: out[n_req] in request order; runs on the context's
+ *     stream and returns when the results are on the host.  Runs of batches
+ *     of one context must not overlap (the context is single-threaded).
+ *   sabr_batch_destroy: waits for the context's stream and frees the batch
+ *     (NULL is ignored). */
+typedef struct sabr_batch sabr_batch;
+int sabr_batch_prepare(sabr_ctx *ctx, int32_t n_req, const sabr_request *reqs, sabr_batch **out);
+int sabr_batch_run(sabr_batch *batch, sabr_result *out);
+void sabr_batch_destroy(sabr_batch *batch);
+
 /* Objective at n_x parameter vectors (Section 3 cost functions).
  *   X[n_x * n_par] row-major parameter vectors, f[n_x] objective values,
  *   model[n_x * n_obs] (may be NULL) model vols or prices.

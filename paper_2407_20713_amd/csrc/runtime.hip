@@ -409,39 +409,93 @@ struct DevGrid {
     MatsD Mt;
 };
 
-// Upload packed grids and run the normalisation kernels.
-int upload_grids(sabr_ctx *c, Packed &pk, DevGrid &g) {
-    pk.offs.push_back((int32_t)pk.K.size());   // closing offset of the last grid
+// Device memory of one launch: the context's reusable buffers, or (for a
+// prepared batch) allocations the batch owns until it is destroyed.
+struct Alloc {
+    sabr_ctx *c;
+    std::vector<void *> *owned = nullptr;
+    int get(int slot, size_t bytes, void **p) {
+        if (!owned) return get_buf(c, slot, bytes, p);
+        if (bytes == 0) bytes = 16;
+        void *q = nullptr;
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            hipGetLastError();
+            return fail(c, SABR_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+        }
+        owned->push_back(q);
+        *p = q;
+        return SABR_OK;
+    }
+    template <typename T>
+    int put(int slot, const std::vector<T> &v, T **out) {
+        void *p;
+        int rc = get(slot, v.size() * sizeof(T), &p);
+        if (rc) return rc;
+        if ((rc = copy_h2d(c, p, v.data(), v.size() * sizeof(T)))) return rc;
+        *out = static_cast<T *>(p);
+        return SABR_OK;
+    }
+};
+
+// Packed raw grids in device memory, and the buffers their normalisation fills.
+struct RawGrid {
     double *K, *fwdp, *betap, *target, *T, *fwd, *betam;
     int32_t *formp, *wghtp, *row, *offs;
+    double *lfk, *lkf, *P1, *Z, *Q1, *Q2, *sw, *lnf, *F1;
+    int np, nm;
+};
+
+// Copy packed grids to the device and reserve the normalised arrays.
+int upload_raw(sabr_ctx *c, Packed &pk, RawGrid &g, Alloc &al) {
+    pk.offs.push_back((int32_t)pk.K.size());   // closing offset of the last grid
     int rc;
-    if ((rc = upload(c, S_K, pk.K, &K)) || (rc = upload(c, S_FWDP, pk.fwdp, &fwdp)) ||
-        (rc = upload(c, S_BETAP, pk.betap, &betap)) || (rc = upload(c, S_TARGET, pk.target, &target)) ||
-        (rc = upload(c, S_T, pk.T, &T)) || (rc = upload(c, S_FWD, pk.fwd, &fwd)) ||
-        (rc = upload(c, S_BETAM, pk.betam, &betam)) || (rc = upload(c, S_FORMP, pk.formp, &formp)) ||
-        (rc = upload(c, S_WGHTP, pk.wghtp, &wghtp)) || (rc = upload(c, S_ROW, pk.row, &row)) ||
-        (rc = upload(c, S_OFFS, pk.offs, &offs)))
+    if ((rc = al.put(S_K, pk.K, &g.K)) || (rc = al.put(S_FWDP, pk.fwdp, &g.fwdp)) ||
+        (rc = al.put(S_BETAP, pk.betap, &g.betap)) || (rc = al.put(S_TARGET, pk.target, &g.target)) ||
+        (rc = al.put(S_T, pk.T, &g.T)) || (rc = al.put(S_FWD, pk.fwd, &g.fwd)) ||
+        (rc = al.put(S_BETAM, pk.betam, &g.betam)) || (rc = al.put(S_FORMP, pk.formp, &g.formp)) ||
+        (rc = al.put(S_WGHTP, pk.wghtp, &g.wghtp)) || (rc = al.put(S_ROW, pk.row, &g.row)) ||
+        (rc = al.put(S_OFFS, pk.offs, &g.offs)))
         return rc;
-    const size_t np = pk.K.size(), nm = pk.T.size();
-    void *lfk, *lkf, *P1, *Z, *Q1, *Q2, *sw, *lnf, *F1;
-    if ((rc = get_buf(c, S_LFK, np * 8, &lfk)) || (rc = get_buf(c, S_LKF, np * 8, &lkf)) ||
-        (rc = get_buf(c, S_P1, np * 8, &P1)) || (rc = get_buf(c, S_Z, np * 8, &Z)) ||
-        (rc = get_buf(c, S_Q1, np * 8, &Q1)) || (rc = get_buf(c, S_Q2, np * 8, &Q2)) ||
-        (rc = get_buf(c, S_SW, np * 8, &sw)) || (rc = get_buf(c, S_LNF, nm * 8, &lnf)) ||
-        (rc = get_buf(c, S_F1, nm * 8, &F1)))
+    g.np = (int)pk.K.size();
+    g.nm = (int)pk.T.size();
+    const size_t np = (size_t)g.np, nm = (size_t)g.nm;
+    void *b[9];
+    if ((rc = al.get(S_LFK, np * 8, &b[0])) || (rc = al.get(S_LKF, np * 8, &b[1])) ||
+        (rc = al.get(S_P1, np * 8, &b[2])) || (rc = al.get(S_Z, np * 8, &b[3])) ||
+        (rc = al.get(S_Q1, np * 8, &b[4])) || (rc = al.get(S_Q2, np * 8, &b[5])) ||
+        (rc = al.get(S_SW, np * 8, &b[6])) || (rc = al.get(S_LNF, nm * 8, &b[7])) ||
+        (rc = al.get(S_F1, nm * 8, &b[8])))
         return rc;
-    int n = (int)np;
-    void *a1[] = {&n, &K, &fwdp, &betap, &formp, &wghtp, &target, &lfk, &lkf, &P1, &Z, &Q1, &Q2, &sw};
+    double **d[9] = {&g.lfk, &g.lkf, &g.P1, &g.Z, &g.Q1, &g.Q2, &g.sw, &g.lnf, &g.F1};
+    for (int i = 0; i < 9; ++i) *d[i] = (double *)b[i];
+    return SABR_OK;
+}
+
+// Grid normalisation (row a1 of the path): per point and per maturity.
+int launch_normalise(sabr_ctx *c, const RawGrid &g, DevGrid &dg) {
+    int rc;
+    int n = g.np;
+    void *a1[] = {&n, (void *)&g.K, (void *)&g.fwdp, (void *)&g.betap, (void *)&g.formp, (void *)&g.wghtp,
+                  (void *)&g.target, (void *)&g.lfk, (void *)&g.lkf, (void *)&g.P1, (void *)&g.Z,
+                  (void *)&g.Q1, (void *)&g.Q2, (void *)&g.sw};
     if ((rc = launch(c, false, "prepare_points", prepare_points_kernel_ptr(), dim3((n + 255) / 256), dim3(256), a1, 0)))
         return rc;
-    int nmi = (int)nm;
-    void *a2[] = {&nmi, &fwd, &betam, &lnf, &F1};
+    int nmi = g.nm;
+    void *a2[] = {&nmi, (void *)&g.fwd, (void *)&g.betam, (void *)&g.lnf, (void *)&g.F1};
     if ((rc = launch(c, false, "prepare_mats", prepare_mats_kernel_ptr(), dim3((nmi + 255) / 256), dim3(256), a2, 0)))
         return rc;
-    g.P = PointsD{(const double *)lfk, (const double *)lkf, (const double *)P1, (const double *)Z,
-                  (const double *)Q1, (const double *)Q2, target, (const double *)sw, row};
-    g.Mt = MatsD{T, (const double *)lnf, (const double *)F1, offs};
+    dg.P = PointsD{g.lfk, g.lkf, g.P1, g.Z, g.Q1, g.Q2, g.target, g.sw, g.row};
+    dg.Mt = MatsD{g.T, g.lnf, g.F1, g.offs};
     return SABR_OK;
+}
+
+// Upload packed grids and run the normalisation kernels.
+int upload_grids(sabr_ctx *c, Packed &pk, DevGrid &g) {
+    Alloc al{c};
+    RawGrid raw;
+    int rc;
+    if ((rc = upload_raw(c, pk, raw, al))) return rc;
+    return launch_normalise(c, raw, g);
 }
 
 void fill_desc(ReqDesc &d, const sabr_market &m, const sabr_problem &p, const sabr_objspec &o, int pt_off,
@@ -515,13 +569,13 @@ int row_split(const sabr_ctx *c, const sabr_request &q, int lpc) {
     return rs;
 }
 
-int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, sabr_result *out) {
+// A request spread over several workgroups needs them all resident at once
+// (level-end exchange); a group too large for that is split into groups of
+// fewer requests that run as consecutive launches (each request's result is
+// unchanged).
+void split_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, std::vector<Group> &out) {
     const int nr = (int)grp.reqs.size();
-    const int lpc = grp.lpc;
-    const int chains_per_wg = kWG / lpc;
-    // A request spread over several workgroups needs them all resident at once
-    // (level-end exchange); a batch too large for that runs as consecutive
-    // launches of fewer requests (each request's result is unchanged).
+    const int chains_per_wg = kWG / grp.lpc;
     if (nr > 1) {
         const bool fp32 = grp.fp32 != 0;
         size_t smem = 0;
@@ -535,7 +589,7 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
             multi |= nwg > 1;
         }
         smem += sa_smem_fixed_bytes();
-        const void *fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0, lpc);
+        const void *fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0, grp.lpc);
         int per_cu = 0;
         if (multi && fn && smem <= c->max_smem) {
             if (smem > 65536) hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
@@ -545,27 +599,55 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
                 Group a = grp, b = grp;
                 a.reqs.assign(grp.reqs.begin(), grp.reqs.begin() + nr / 2);
                 b.reqs.assign(grp.reqs.begin() + nr / 2, grp.reqs.end());
-                int rc = run_formula_group(c, reqs, a, out);
-                return rc ? rc : run_formula_group(c, reqs, b, out);
+                split_group(c, reqs, a, out);
+                split_group(c, reqs, b, out);
+                return;
             }
         }
     }
+    out.push_back(grp);
+}
+
+// Host side of one annealing launch: packed grids, descriptors, schedules,
+// workgroup map, kernels and their LDS sizes.
+struct GroupPlan {
+    Group grp;
     Packed pk;
-    std::vector<ReqDesc> desc(nr);
+    std::vector<ReqDesc> desc;
     std::vector<double> sg, sh;
-    std::vector<int32_t> wg_req;
+    std::vector<int32_t> wg_req, pol;
     int cand_slots = 0;
+    size_t smem = 0, psm = 0;
+    bool multi_wg = false;
+    const void *fn = nullptr, *pf = nullptr;
+};
+
+// Device side of one annealing launch.
+struct GroupDev {
+    RawGrid raw;
+    ReqDesc *dreq = nullptr;
+    int32_t *dwg = nullptr, *dpol = nullptr;
+    double *dsg = nullptr, *dsh = nullptr;
+    void *cand = nullptr, *best = nullptr, *acc = nullptr, *err = nullptr, *evals = nullptr;
+};
+
+int plan_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, GroupPlan &pl) {
+    const int nr = (int)grp.reqs.size();
+    const int lpc = grp.lpc;
+    const int chains_per_wg = kWG / lpc;
+    pl.grp = grp;
+    pl.desc.resize(nr);
     for (int r = 0; r < nr; ++r) {
         const sabr_request &q = reqs[grp.reqs[r]];
         int pt_off, mat_off;
-        pack_grid(pk, q.market, q.problem, q.obj, pt_off, mat_off);
-        ReqDesc &d = desc[r];
+        pack_grid(pl.pk, q.market, q.problem, q.obj, pt_off, mat_off);
+        ReqDesc &d = pl.desc[r];
         fill_desc(d, q.market, q.problem, q.obj, pt_off, mat_off);
         d.n_chains = q.sa.n_chains;
         d.n_iters = q.sa.n_iters;
         d.chain_len = q.sa.chain_len;
         d.n_levels = (q.sa.n_iters + q.sa.chain_len - 1) / q.sa.chain_len;
-        d.sched_off = (int)sg.size();
+        d.sched_off = (int)pl.sg.size();
         d.polish = q.sa.polish;
         d.rsplit = row_split(c, q, lpc);
         d.key0 = (uint32_t)(q.sa.seed & 0xffffffffu);
@@ -574,102 +656,121 @@ int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, s
         const double cL = std::pow(q.sa.cooling, (double)q.sa.chain_len);
         double g = 1.0;
         for (int k = 0; k < d.n_levels; ++k) {
-            sg.push_back(g);
-            sh.push_back(std::fmax(q.sa.step0 * std::sqrt(g), q.sa.step_min));
+            pl.sg.push_back(g);
+            pl.sh.push_back(std::fmax(q.sa.step0 * std::sqrt(g), q.sa.step_min));
             g = g * cL;
         }
         d.n_wg = (q.sa.n_chains + chains_per_wg - 1) / chains_per_wg;
-        d.wg_first = (int)wg_req.size();
-        for (int w = 0; w < d.n_wg; ++w) wg_req.push_back(r);
-        d.cand_off = cand_slots;
-        cand_slots += 2 * d.n_wg;
+        d.wg_first = (int)pl.wg_req.size();
+        for (int w = 0; w < d.n_wg; ++w) pl.wg_req.push_back(r);
+        d.cand_off = pl.cand_slots;
+        pl.cand_slots += 2 * d.n_wg;
+        if (d.polish) pl.pol.push_back(r);
+        pl.multi_wg |= d.n_wg > 1;
     }
-    int rc;
-    DevGrid g;
-    if ((rc = upload_grids(c, pk, g))) return rc;
-    ReqDesc *dreq;
-    int32_t *dwg;
-    double *dsg, *dsh;
-    if ((rc = upload(c, S_REQ, desc, &dreq)) || (rc = upload(c, S_WGREQ, wg_req, &dwg)) ||
-        (rc = upload(c, S_SCHED_G, sg, &dsg)) || (rc = upload(c, S_SCHED_H, sh, &dsh)))
-        return rc;
-    void *cand, *best, *acc, *err, *evals;
-    if ((rc = get_buf(c, S_CAND, sizeof(Cand) * std::max(cand_slots, 1), &cand)) ||
-        (rc = get_buf(c, S_BEST, sizeof(ChainOut) * nr, &best)) ||
-        (rc = get_buf(c, S_ACC, sizeof(unsigned long long) * nr, &acc)) ||
-        (rc = get_buf(c, S_ERR, sizeof(int32_t), &err)) ||
-        (rc = get_buf(c, S_EVALS, sizeof(unsigned long long) * nr, &evals)))
-        return rc;
-    HIPCHK(c, hipMemsetAsync(cand, 0, sizeof(Cand) * std::max(cand_slots, 1), c->stream));   // exchange tags
-    HIPCHK(c, hipMemsetAsync(acc, 0, sizeof(unsigned long long) * nr, c->stream));
-    HIPCHK(c, hipMemsetAsync(err, 0, sizeof(int32_t), c->stream));
-    HIPCHK(c, hipMemsetAsync(evals, 0, sizeof(unsigned long long) * nr, c->stream));
-
     const bool fp32 = grp.fp32 != 0;
     // the polish stages the double grid: refuse a grid it cannot hold before annealing
     for (int r = 0; r < nr; ++r) {
-        const size_t psm = grid_smem_bytes(false, desc[r].n_pts, desc[r].n_mat) + sizeof(int32_t) * desc[r].n_pts;
-        if (desc[r].polish && psm > c->max_smem)
+        const size_t psm = grid_smem_bytes(false, pl.desc[r].n_pts, pl.desc[r].n_mat) + sizeof(int32_t) * pl.desc[r].n_pts;
+        if (pl.desc[r].polish && psm > c->max_smem)
             return fail(c, SABR_E_INVAL, "the polish needs %zu bytes of LDS for this grid, the device has %zu", psm,
                         c->max_smem);
+        if (pl.desc[r].polish) pl.psm = std::max(pl.psm, psm);
     }
-    size_t smem = 0;
-    for (int r = 0; r < nr; ++r) smem = std::max(smem, grid_smem_bytes(fp32, desc[r].n_pts, desc[r].n_mat));
-    smem += sa_smem_fixed_bytes();
-    const void *fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0, lpc);
-    if (!fn) return fail(c, SABR_E_INVAL, "no kernel for model %d formula %d", grp.model, grp.formula);
-    if ((rc = set_smem(c, fn, smem))) return rc;
-    const int n_blocks = (int)wg_req.size();
-    bool multi_wg = false;
-    for (int r = 0; r < nr; ++r) multi_wg |= desc[r].n_wg > 1;
-    if (multi_wg) {
+    for (int r = 0; r < nr; ++r) pl.smem = std::max(pl.smem, grid_smem_bytes(fp32, pl.desc[r].n_pts, pl.desc[r].n_mat));
+    pl.smem += sa_smem_fixed_bytes();
+    pl.fn = sa_kernel_ptr(grp.model, grp.formula, fp32, grp.bfree != 0, lpc);
+    if (!pl.fn) return fail(c, SABR_E_INVAL, "no kernel for model %d formula %d", grp.model, grp.formula);
+    int rc;
+    if ((rc = set_smem(c, pl.fn, pl.smem))) return rc;
+    if (pl.multi_wg) {
         int per_cu = 0;
-        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWG, smem));
-        if ((int64_t)per_cu * c->n_cu < n_blocks)
+        HIPCHK(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, pl.fn, kWG, pl.smem));
+        if ((int64_t)per_cu * c->n_cu < (int64_t)pl.wg_req.size())
             return fail(c, SABR_E_BUDGET,
                         "%d annealing workgroups cannot be resident at once (%d per CU x %d CUs); split the batch",
-                        n_blocks, per_cu, c->n_cu);
+                        (int)pl.wg_req.size(), per_cu, c->n_cu);
     }
+    if (!pl.pol.empty()) {
+        pl.pf = polish_kernel_ptr(grp.model, grp.formula, grp.bfree != 0);
+        if ((rc = set_smem(c, pl.pf, pl.psm))) return rc;
+    }
+    return SABR_OK;
+}
+
+int upload_group(sabr_ctx *c, GroupPlan &pl, GroupDev &gd, Alloc &al) {
+    const int nr = (int)pl.desc.size();
+    int rc;
+    if ((rc = upload_raw(c, pl.pk, gd.raw, al))) return rc;
+    if ((rc = al.put(S_REQ, pl.desc, &gd.dreq)) || (rc = al.put(S_WGREQ, pl.wg_req, &gd.dwg)) ||
+        (rc = al.put(S_SCHED_G, pl.sg, &gd.dsg)) || (rc = al.put(S_SCHED_H, pl.sh, &gd.dsh)))
+        return rc;
+    if (!pl.pol.empty() && (rc = al.put(S_POLREQ, pl.pol, &gd.dpol))) return rc;
+    if ((rc = al.get(S_CAND, sizeof(Cand) * std::max(pl.cand_slots, 1), &gd.cand)) ||
+        (rc = al.get(S_BEST, sizeof(ChainOut) * nr, &gd.best)) ||
+        (rc = al.get(S_ACC, sizeof(unsigned long long) * nr, &gd.acc)) ||
+        (rc = al.get(S_ERR, sizeof(int32_t), &gd.err)) ||
+        (rc = al.get(S_EVALS, sizeof(unsigned long long) * nr, &gd.evals)))
+        return rc;
+    return SABR_OK;
+}
+
+// Grid normalisation, annealing, polish and results of one planned launch;
+// out is indexed like the requests the group was planned from.
+int exec_group(sabr_ctx *c, const GroupPlan &pl, GroupDev &gd, sabr_result *out) {
+    const int nr = (int)pl.desc.size();
+    int rc;
+    DevGrid g;
+    if ((rc = launch_normalise(c, gd.raw, g))) return rc;
+    HIPCHK(c, hipMemsetAsync(gd.cand, 0, sizeof(Cand) * std::max(pl.cand_slots, 1), c->stream));   // exchange tags
+    HIPCHK(c, hipMemsetAsync(gd.acc, 0, sizeof(unsigned long long) * nr, c->stream));
+    HIPCHK(c, hipMemsetAsync(gd.err, 0, sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(gd.evals, 0, sizeof(unsigned long long) * nr, c->stream));
     PointsD P = g.P;
     MatsD Mt = g.Mt;
-    void *args[] = {&dreq, &dwg, &P, &Mt, &dsg, &dsh, &cand, &best, &acc, &err};
-    if ((rc = launch(c, true, "sa_kernel", fn, dim3(n_blocks), dim3(kWG), args, smem, multi_wg))) return rc;
-
+    void *args[] = {&gd.dreq, &gd.dwg, &P, &Mt, &gd.dsg, &gd.dsh, &gd.cand, &gd.best, &gd.acc, &gd.err};
+    if ((rc = launch(c, true, "sa_kernel", pl.fn, dim3((unsigned)pl.wg_req.size()), dim3(kWG), args, pl.smem,
+                     pl.multi_wg)))
+        return rc;
     std::vector<ChainOut> hpre(nr);
-    HIPCHK(c, hipMemcpyAsync(hpre.data(), best, sizeof(ChainOut) * nr, hipMemcpyDeviceToHost, c->stream));
-    // polish
-    std::vector<int32_t> pol;
-    for (int r = 0; r < nr; ++r)
-        if (desc[r].polish) pol.push_back(r);
-    if (!pol.empty()) {
-        int32_t *dpol;
-        if ((rc = upload(c, S_POLREQ, pol, &dpol))) return rc;
-        size_t psm = 0;
-        for (int r : pol)
-            psm = std::max(psm, grid_smem_bytes(false, desc[r].n_pts, desc[r].n_mat) + sizeof(int32_t) * desc[r].n_pts);
-        const void *pf = polish_kernel_ptr(grp.model, grp.formula, grp.bfree != 0);
-        if ((rc = set_smem(c, pf, psm))) return rc;
-        void *pargs[] = {&dreq, &dpol, &P, &Mt, &best, &evals};
-        if ((rc = launch(c, false, "polish_kernel", pf, dim3((unsigned)pol.size()), dim3(64), pargs, psm))) return rc;
+    HIPCHK(c, hipMemcpyAsync(hpre.data(), gd.best, sizeof(ChainOut) * nr, hipMemcpyDeviceToHost, c->stream));
+    if (!pl.pol.empty()) {
+        void *pargs[] = {&gd.dreq, &gd.dpol, &P, &Mt, &gd.best, &gd.evals};
+        if ((rc = launch(c, false, "polish_kernel", pl.pf, dim3((unsigned)pl.pol.size()), dim3(64), pargs, pl.psm)))
+            return rc;
     }
     std::vector<ChainOut> hb(nr);
     std::vector<unsigned long long> ha(nr), he(nr);
     int32_t herr = 0;
-    HIPCHK(c, hipMemcpyAsync(hb.data(), best, sizeof(ChainOut) * nr, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(ha.data(), acc, sizeof(unsigned long long) * nr, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(he.data(), evals, sizeof(unsigned long long) * nr, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(hb.data(), gd.best, sizeof(ChainOut) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ha.data(), gd.acc, sizeof(unsigned long long) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(he.data(), gd.evals, sizeof(unsigned long long) * nr, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&herr, gd.err, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     if ((rc = sync_and_account(c))) return rc;
     if (herr) return fail(c, SABR_E_TIMEOUT, "a workgroup of the annealing kernel exceeded its wait bound");
     for (int r = 0; r < nr; ++r) {
-        sabr_result &o = out[grp.reqs[r]];
+        sabr_result &o = out[pl.grp.reqs[r]];
         std::memset(&o, 0, sizeof o);
-        for (int k = 0; k < desc[r].n_par; ++k) o.x[k] = hb[r].bx[k];
+        for (int k = 0; k < pl.desc[r].n_par; ++k) o.x[k] = hb[r].bx[k];
         o.f = hb[r].bf;
         o.f_before_polish = hpre[r].bf;
         o.n_accept = (int64_t)ha[r];
-        o.n_evals = 1 + (int64_t)desc[r].n_chains * desc[r].n_iters + (int64_t)he[r];
+        o.n_evals = 1 + (int64_t)pl.desc[r].n_chains * pl.desc[r].n_iters + (int64_t)he[r];
         o.status = SABR_OK;
+    }
+    return SABR_OK;
+}
+
+int run_formula_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, sabr_result *out) {
+    std::vector<Group> parts;
+    split_group(c, reqs, grp, parts);
+    for (const Group &g : parts) {
+        GroupPlan pl;
+        GroupDev gd;
+        Alloc al{c};
+        int rc;
+        if ((rc = plan_group(c, reqs, g, pl)) || (rc = upload_group(c, pl, gd, al)) || (rc = exec_group(c, pl, gd, out)))
+            return rc;
     }
     return SABR_OK;
 }
@@ -855,11 +956,76 @@ int run_mc_request(sabr_ctx *c, const sabr_request &q, sabr_result &out) {
     return SABR_OK;
 }
 
+// Validation of a calibration call: out[r].status gets each request's error.
+int validate_requests(sabr_ctx *c, int n_req, const sabr_request *reqs, sabr_result *out) {
+    int bad = 0;
+    std::string first_err;
+    for (int r = 0; r < n_req; ++r) {
+        const sabr_request &q = reqs[r];
+        std::memset(&out[r], 0, sizeof out[r]);
+        int rc;
+        const bool mc = q.obj.kind == SABR_OBJ_MC;
+        if ((rc = check_request(c, q))) {
+            out[r].status = rc;
+            if (!bad) first_err = c->err;
+            ++bad;
+            continue;
+        }
+        if (q.problem.model == SABR_DYN_II && !mc) {
+            double x0[kMaxPar], tmax = 0;
+            for (int k = 0; k < q.problem.n_par; ++k)
+                x0[k] = q.problem.x0 ? q.problem.x0[k] : 0.5 * (q.problem.lb[k] + q.problem.ub[k]);
+            for (int i = 0; i < q.market.n_mat; ++i) tmax = std::max(tmax, q.market.T[i]);
+            if (!case2_ok_host(x0, tmax)) {
+                out[r].status = SABR_E_INFEASIBLE;
+                if (!bad) first_err = "case II start point violates the constraints";
+                ++bad;
+            }
+        }
+    }
+    if (bad) {
+        c->err = first_err;
+        return SABR_E_INVAL;
+    }
+    return SABR_OK;
+}
+
+// Formula requests grouped by kernel variant, in request order.
+void group_formula_requests(sabr_ctx *c, int n_req, const sabr_request *reqs, std::vector<Group> &groups) {
+    for (int r = 0; r < n_req; ++r) {
+        const sabr_request &q = reqs[r];
+        if (q.obj.kind != SABR_OBJ_FORMULA) continue;
+        const int formula = q.problem.model == SABR_STATIC ? q.obj.formula : F_HAGAN;
+        const int fp32 = q.obj.precision == SABR_FP32;
+        const int bfree = q.problem.beta_free ? 1 : 0;
+        const int lpc = lanes_per_chain(c, q);
+        Group *gp = nullptr;
+        for (auto &g : groups)
+            if (g.model == q.problem.model && g.formula == formula && g.fp32 == fp32 && g.bfree == bfree &&
+                g.lpc == lpc)
+                gp = &g;
+        if (!gp) {
+            groups.push_back(Group{q.problem.model, formula, fp32, bfree, lpc, {}});
+            gp = &groups.back();
+        }
+        gp->reqs.push_back(r);
+    }
+}
+
 }  // namespace
 
 // =====================================================================================
 // C ABI
 // =====================================================================================
+// A prepared batch: the plans and device inputs of its annealing launches.
+struct sabr_batch {
+    sabr_ctx *ctx = nullptr;
+    int n_req = 0;
+    std::vector<GroupPlan> plans;
+    std::vector<GroupDev> devs;
+    std::vector<void *> owned;   // device allocations, freed by sabr_batch_destroy
+};
+
 extern "C" {
 
 int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx **out) {
@@ -986,73 +1152,92 @@ int sabr_calibrate(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_re
     if (n_req < 1 || !reqs || !out) return fail(c, SABR_E_INVAL, "need n_req >= 1 and non-NULL arrays");
     c->err.clear();
     hipSetDevice(c->device);
-    int bad = 0;
-    std::string first_err;
-    for (int r = 0; r < n_req; ++r) {
-        const sabr_request &q = reqs[r];
-        std::memset(&out[r], 0, sizeof out[r]);
-        int rc;
-        const bool mc = q.obj.kind == SABR_OBJ_MC;
-        if ((rc = check_obj(c, &q.obj, q.problem.model)) || (rc = check_problem(c, &q.problem, true)) ||
-            (rc = check_market(c, &q.market, true, mc, q.obj.weighting)) || (rc = check_sa(c, &q.sa)) ||
-            (mc && (rc = check_mc(c, &q.mc)))) {
-            out[r].status = rc;
-            if (!bad) first_err = c->err;
-            ++bad;
-            continue;
-        }
-        if (q.problem.model == SABR_DYN_II && !mc) {
-            double x0[kMaxPar], tmax = 0;
-            for (int k = 0; k < q.problem.n_par; ++k)
-                x0[k] = q.problem.x0 ? q.problem.x0[k] : 0.5 * (q.problem.lb[k] + q.problem.ub[k]);
-            for (int i = 0; i < q.market.n_mat; ++i) tmax = std::max(tmax, q.market.T[i]);
-            if (!case2_ok_host(x0, tmax)) {
-                out[r].status = SABR_E_INFEASIBLE;
-                if (!bad) first_err = "case II start point violates the constraints";
-                ++bad;
-            }
-        }
-    }
-    if (bad) {
-        c->err = first_err;
-        return SABR_E_INVAL;
-    }
-    // group formula requests by kernel variant
+    int rc;
+    if ((rc = validate_requests(c, n_req, reqs, out))) return rc;
     std::vector<Group> groups;
-    for (int r = 0; r < n_req; ++r) {
-        const sabr_request &q = reqs[r];
-        if (q.obj.kind != SABR_OBJ_FORMULA) continue;
-        const int formula = q.problem.model == SABR_STATIC ? q.obj.formula : F_HAGAN;
-        const int fp32 = q.obj.precision == SABR_FP32;
-        const int bfree = q.problem.beta_free ? 1 : 0;
-        const int lpc = lanes_per_chain(c, q);
-        Group *gp = nullptr;
-        for (auto &g : groups)
-            if (g.model == q.problem.model && g.formula == formula && g.fp32 == fp32 && g.bfree == bfree &&
-                g.lpc == lpc)
-                gp = &g;
-        if (!gp) {
-            groups.push_back(Group{q.problem.model, formula, fp32, bfree, lpc, {}});
-            gp = &groups.back();
-        }
-        gp->reqs.push_back(r);
-    }
+    group_formula_requests(c, n_req, reqs, groups);
     for (auto &g : groups) {
-        int rc = run_formula_group(c, reqs, g, out);
-        if (rc) {
+        if ((rc = run_formula_group(c, reqs, g, out))) {
             for (int r : g.reqs) out[r].status = rc;
             return rc;
         }
     }
     for (int r = 0; r < n_req; ++r) {
         if (reqs[r].obj.kind != SABR_OBJ_MC) continue;
-        int rc = run_mc_request(c, reqs[r], out[r]);
-        if (rc) {
+        if ((rc = run_mc_request(c, reqs[r], out[r]))) {
             out[r].status = rc;
             return rc;
         }
     }
     return SABR_OK;
+}
+
+int sabr_batch_prepare(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_batch **out) {
+    if (!c) return SABR_E_INVAL;
+    if (!out) return fail(c, SABR_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n_req < 1 || !reqs) return fail(c, SABR_E_INVAL, "need n_req >= 1 and a non-NULL request array");
+    c->err.clear();
+    hipSetDevice(c->device);
+    for (int r = 0; r < n_req; ++r)
+        if (reqs[r].obj.kind == SABR_OBJ_MC)
+            return fail(c, SABR_E_INVAL, "request %d uses the Monte Carlo objective; a prepared batch holds formula "
+                                         "requests only (use sabr_calibrate)", r);
+    std::vector<sabr_result> tmp(n_req);
+    int rc;
+    if ((rc = validate_requests(c, n_req, reqs, tmp.data()))) return rc;
+    std::vector<Group> groups, parts;
+    group_formula_requests(c, n_req, reqs, groups);
+    for (const Group &g : groups) split_group(c, reqs, g, parts);
+    sabr_batch *b = new sabr_batch;
+    b->ctx = c;
+    b->n_req = n_req;
+    b->plans.resize(parts.size());
+    b->devs.resize(parts.size());
+    for (size_t i = 0; i < parts.size() && !rc; ++i) {
+        Alloc al{c, &b->owned};
+        if ((rc = plan_group(c, reqs, parts[i], b->plans[i]))) break;
+        if ((rc = upload_group(c, b->plans[i], b->devs[i], al))) break;
+        // the host copies of the grids are no longer needed
+        b->plans[i].pk = Packed{};
+    }
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) {
+        hipGetLastError();
+        rc = fail(c, SABR_E_DEVICE, "upload of the batch failed");
+    }
+    if (rc) {
+        sabr_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return SABR_OK;
+}
+
+int sabr_batch_run(sabr_batch *b, sabr_result *out) {
+    if (!b) return SABR_E_INVAL;
+    sabr_ctx *c = b->ctx;
+    if (!out) return fail(c, SABR_E_INVAL, "out is NULL");
+    c->err.clear();
+    hipSetDevice(c->device);
+    for (int r = 0; r < b->n_req; ++r) std::memset(&out[r], 0, sizeof out[r]);
+    for (size_t i = 0; i < b->plans.size(); ++i) {
+        const GroupPlan &pl = b->plans[i];
+        int rc;
+        if ((rc = set_smem(c, pl.fn, pl.smem)) || (!pl.pol.empty() && (rc = set_smem(c, pl.pf, pl.psm))) ||
+            (rc = exec_group(c, pl, b->devs[i], out))) {
+            for (int r : pl.grp.reqs) out[r].status = rc;
+            return rc;
+        }
+    }
+    return SABR_OK;
+}
+
+void sabr_batch_destroy(sabr_batch *b) {
+    if (!b) return;
+    hipSetDevice(b->ctx->device);
+    hipStreamSynchronize(b->ctx->stream);
+    for (void *p : b->owned) hipFree(p);
+    delete b;
 }
 
 int sabr_objective_batch(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem,

@@ -26,7 +26,8 @@ SABR_FP64, SABR_FP32 = 0, 1
 
 EXPORTED = ["sabr_ctx_create", "sabr_ctx_destroy", "sabr_ctx_last_error", "sabr_ctx_set_workspace",
             "sabr_ctx_enable_timing",
-            "sabr_ctx_timing", "sabr_calibrate", "sabr_objective_batch", "sabr_mc_price",
+            "sabr_ctx_timing", "sabr_calibrate", "sabr_batch_prepare", "sabr_batch_run", "sabr_batch_destroy",
+            "sabr_objective_batch", "sabr_mc_price",
             "sabr_server_create", "sabr_server_submit", "sabr_server_poll", "sabr_server_cancel",
             "sabr_server_stats", "sabr_server_destroy"]
 
@@ -103,6 +104,10 @@ def lib():
         L.sabr_ctx_enable_timing.argtypes = [C.c_void_p, C.c_int]
         L.sabr_ctx_timing.argtypes = [C.c_void_p, C.c_int, _D, C.POINTER(C.c_int64), C.c_char_p, C.c_size_t]
         L.sabr_calibrate.argtypes = [C.c_void_p, C.c_int32, C.POINTER(sabr_request), C.POINTER(sabr_result)]
+        L.sabr_batch_prepare.argtypes = [C.c_void_p, C.c_int32, C.POINTER(sabr_request), C.POINTER(C.c_void_p)]
+        L.sabr_batch_run.argtypes = [C.c_void_p, C.POINTER(sabr_result)]
+        L.sabr_batch_destroy.argtypes = [C.c_void_p]
+        L.sabr_batch_destroy.restype = None
         L.sabr_objective_batch.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem),
                                            C.POINTER(sabr_objspec), C.POINTER(sabr_mc), C.c_int64, C.c_void_p,
                                            C.c_void_p, C.c_void_p]
@@ -179,6 +184,8 @@ class Ctx:
 
     def close(self):
         if self.h:
+            for b in list(getattr(self, "batches", ())):
+                b.close()
             lib().sabr_ctx_destroy(self.h)
             self.h = None
 
@@ -259,12 +266,62 @@ def sabr_calibrate(ctx, requests):
     rc = lib().sabr_calibrate(ctx.h, n, arr, out)
     if rc != SABR_OK:
         raise SabrError(rc, lib().sabr_ctx_last_error(ctx.h).decode())
+    return _results(requests, out)
+
+
+def _results(requests, out):
     res = []
     for r, o in zip(requests, out):
         d = r.problem.n_par
         res.append(dict(x=np.array(o.x[:d]), f=o.f, f_before_polish=o.f_before_polish, n_evals=o.n_evals,
                         n_accept=o.n_accept, status=o.status))
     return res
+
+
+class Batch:
+    """Owning handle of a prepared batch (destroyed before its context)."""
+
+    def __init__(self, ctx, requests):
+        self.ctx, self.h = ctx, None
+        self.requests = list(requests)
+        n = len(self.requests)
+        arr = (sabr_request * n)(*[r.c() for r in self.requests])
+        h = C.c_void_p()
+        ctx.check(lib().sabr_batch_prepare(ctx.h, n, arr, C.byref(h)))
+        self.h = h
+        self.out = (sabr_result * n)()
+        if not hasattr(ctx, "batches"):
+            import weakref
+            ctx.batches = weakref.WeakSet()
+        ctx.batches.add(self)
+
+    def close(self):
+        if self.h:
+            lib().sabr_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sabr_batch_prepare(ctx, requests):
+    """Validate and upload a list of formula-objective Request; returns a Batch."""
+    return Batch(ctx, requests)
+
+
+def sabr_batch_run(batch, raw=False):
+    """Run a prepared batch; returns a list of dicts like sabr_calibrate (the
+    ctypes result array itself with raw=True)."""
+    rc = lib().sabr_batch_run(batch.h, batch.out)
+    batch.ctx.check(rc)
+    return batch.out if raw else _results(batch.requests, batch.out)
+
+
+def sabr_batch_destroy(batch):
+    batch.close()
 
 
 def _ptr(a):

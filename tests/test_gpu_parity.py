@@ -567,3 +567,51 @@ def test_polish_grid_too_large_is_rejected_before_annealing(S, ctx):
     r = S.sabr_calibrate(ctx, [S.Request(mk, S.Problem(S.SABR_STATIC, 0.7, lb, ub), precision=S.SABR_FP32,
                                          n_chains=64, n_iters=10, polish=False)])[0]
     assert r["status"] == 0 and np.isfinite(r["f"])
+
+
+def test_prepared_batch_repeats_calibrate_bitwise(S, ctx, oracle):
+    """A prepared batch (inputs uploaded once) returns, run after run, exactly
+    what sabr_calibrate returns for the same requests: mixed models,
+    precisions and polish, and a group large enough to run in resident parts."""
+    g = inputs.dynamic_surface()
+    m = omkt(oracle, g)
+    lb, ub = inputs.box(inputs.DYN_I)
+    rng = np.random.default_rng(12)
+    reqs = []
+    for k in range(40):
+        xt = lb + (ub - lb) * (0.25 + 0.5 * rng.random(len(lb)))
+        tgt = oracle.model_vols(m, inputs.DYN_I, xt, 0.7)
+        reqs.append(S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_DYN_I, 0.7, lb, ub),
+                              precision=S.SABR_FP32, n_chains=1024, n_iters=20, seed=700 + k))
+    for prec, pol in ((S.SABR_FP32, True), (S.SABR_FP64, False)):
+        req, _, _, _ = smile_request(S, oracle, np.array([0.2, -0.3, 0.5]), 1e-4, prec, 512, 300, 41, polish=pol)
+        reqs.append(req)
+    ref = S.sabr_calibrate(ctx, reqs)
+    b = S.sabr_batch_prepare(ctx, reqs)
+    try:
+        for rep in range(2):
+            got = S.sabr_batch_run(b)
+            for r, (a, e) in enumerate(zip(got, ref)):
+                assert a["status"] == 0, (rep, r)
+                assert np.array_equal(a["x"], e["x"]) and a["f"] == e["f"], (rep, r)
+                assert a["f_before_polish"] == e["f_before_polish"] and a["n_accept"] == e["n_accept"], (rep, r)
+                assert a["n_evals"] == e["n_evals"], (rep, r)
+            # work of the context between runs leaves the batch unchanged
+            S.sabr_calibrate(ctx, reqs[-1:])
+    finally:
+        S.sabr_batch_destroy(b)
+
+
+def test_prepared_batch_refuses_mc_and_invalid(S, ctx):
+    g = inputs.make_grid([0.5], [np.exp(np.linspace(-0.2, 0.2, 5))], f0=1.0)
+    lb, ub = inputs.box(inputs.STATIC)
+    mc = S.Request(S.Market.from_grid(g, target=np.full(5, 0.05)), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                   kind=S.SABR_OBJ_MC, n_chains=64, n_iters=10, n_paths=1024)
+    with pytest.raises(S.SabrError) as e:
+        S.sabr_batch_prepare(ctx, [mc])
+    assert e.value.code == S.SABR_E_INVAL and "Monte Carlo" in str(e.value)
+    bad = S.Request(S.Market.from_grid(g, target=np.full(5, 0.2)), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    n_chains=0, n_iters=10)
+    with pytest.raises(S.SabrError) as e:
+        S.sabr_batch_prepare(ctx, [bad])
+    assert e.value.code == S.SABR_E_INVAL
