@@ -51,6 +51,8 @@ SLOTS_PER_PT_EVAL = 39
 SA_FETCH_KIB, SA_WRITE_KIB = 1092586.4375, 147841.458333
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.1587, 1.0
 SA_TRAFFIC_BYTES = (SA_FETCH_KIB * FETCH_SCALE + SA_WRITE_KIB * WRITE_SCALE) * 1024
+# the counters above were taken before the last change of sa_kernel: not reported
+SA_COUNTERS_CURRENT = False
 SLOTS_SA_PER_ITER = 200
 
 
@@ -405,7 +407,7 @@ def main():
                         "identical_results": same},
         "max_param_error_vs_truth": param_err,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": SA_TRAFFIC_BYTES,
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": SA_TRAFFIC_BYTES if SA_COUNTERS_CURRENT else None,
                      "kernel": kname, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches},
     }
     if not args.no_mc:

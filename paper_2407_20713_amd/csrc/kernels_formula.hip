@@ -100,9 +100,10 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
     const double beta = rq.beta, tmax = rq.t_max;
     const int rsplit = rq.rsplit;
     const uint32_t k0 = rq.key0, k1 = rq.key1;
+    const Row<R> r0 = rows[0];   // the first row's record, kept in registers
     auto f_of = [&](const double *v) {
         double part = objective<MODEL, FORMULA, R, BFREE, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub,
-                                                                      rsplit);
+                                                                      rsplit, r0, true);
         return group_sum<LPC>(part);
     };
 

@@ -132,24 +132,25 @@ __device__ __forceinline__ double x_over_z_series(double z, double rho) {
 }
 
 // Coefficients c_n = P_n(rho) / (n + 1) of the same series, for evaluating it
-// at many z with one rho (Horner in z).
-template <int NT>
+// at many z with one rho (Horner in z).  In float for the float bulk: the
+// terms fall off as 0.05^n, so the sum is accurate to a few float roundings.
+template <typename T, int NT>
 struct XzSeries {
-    double c[NT];
-    __device__ __forceinline__ void init(double rho) {
-        double pm = 1.0, p = rho;
-        c[0] = 1.0;
-        c[1] = 0.5 * rho;
+    T c[NT];
+    __device__ __forceinline__ void init(T rho) {
+        T pm = (T)1, p = rho;
+        c[0] = (T)1;
+        c[1] = (T)0.5 * rho;
 #pragma unroll
         for (int n = 1; n < NT - 1; ++n) {
-            const double pn = fma((double)(2 * n + 1) / (double)(n + 1) * rho, p, -(double)n / (double)(n + 1) * pm);
-            c[n + 1] = pn * (1.0 / (double)(n + 2));
+            const T pn = fma((T)(2 * n + 1) / (T)(n + 1) * rho, p, -(T)n / (T)(n + 1) * pm);
+            c[n + 1] = pn * ((T)1 / (T)(n + 2));
             pm = p;
             p = pn;
         }
     }
-    __device__ __forceinline__ double eval(double z) const {
-        double s = c[NT - 1];
+    __device__ __forceinline__ T eval(T z) const {
+        T s = c[NT - 1];
 #pragma unroll
         for (int n = NT - 2; n >= 0; --n) s = fma(s, z, c[n]);
         return s;

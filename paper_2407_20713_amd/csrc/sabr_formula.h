@@ -9,8 +9,8 @@ namespace sabr {
 // LDS point record (one per strike) and row record (one per maturity).
 template <typename R>
 struct alignas(16) Pt {
-    R P1, Z, Q1, Q2;      // beta fixed: leading factor, z factor, (Kf)^-(1-b)/2, (Kf)^-(1-b)
-    R lfk, lkf, T, pad;   // ln(f/K), ln(Kf), maturity
+    R Z, PZ, Q1, Q2;      // beta fixed: z factor, P1 Z, (Kf)^-(1-b)/2, (Kf)^-(1-b)
+    R P1, lfk, lkf, T;    // leading factor, ln(f/K), ln(Kf), maturity
     double tsw, sw;       // market value times sqrt(weight), sqrt(weight)
 };
 template <typename R>
@@ -70,12 +70,12 @@ __device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const Mat
         Pt<R> p;
         p.P1 = (R)P.P1[g];
         p.Z = (R)P.Z[g];
+        p.PZ = (R)(P.P1[g] * P.Z[g]);
         p.Q1 = (R)P.Q1[g];
         p.Q2 = (R)P.Q2[g];
         p.lfk = (R)P.lfk[g];
         p.lkf = (R)P.lkf[g];
         p.T = (R)Mt.T[P.row[g]];
-        p.pad = (R)0;
         p.sw = P.sw[g];
         p.tsw = P.target[g] * p.sw;
         pts[j] = p;
@@ -142,12 +142,13 @@ template <int MODEL, int FORMULA, typename R, bool BFREE>
 struct ModelEval {
     R al, rh, nu, beta, omb;
     R noa, c1a2, c2rna, c3n2, lr1, lr2, d1, d2;   // z-form static formulas
+    R an, lb1, lb2, omr2;                         // float hot loop: nu / ln 2, log2(1 -/+ rho), 1 - rho^2
     R F1;                                         // f^(1-beta) of the current row
     Quad<R> q;                                    // expansion / dynamic row block
     // near-the-money x(z)/z (float bulk): |z| < 0.05 and |P_n(rho)| <= 1, so
     // six terms leave a truncation below 0.05^6 / 7 = 2.3e-9, under the float
     // rounding of the result
-    XzSeries<6> xs;
+    XzSeries<float, 6> xs;
     const double *y;
 
     // Returns false for a case II vector outside rho(t) in [-1,1], nu(t) > 0.
@@ -168,11 +169,20 @@ struct ModelEval {
             c1a2 = omb * omb * (R)(1.0 / 24.0) * al * al;
             c2rna = beta * (R)0.25 * rh * nu * al;
             c3n2 = ((R)2 - (R)3 * rh * rh) * (R)(1.0 / 24.0) * nu * nu;
-            lr1 = M<R>::lg((R)1 - rh);
-            lr2 = M<R>::lg((R)1 + rh);
+            if constexpr (sizeof(R) == 4) {
+                lb1 = __builtin_amdgcn_logf(1.0f - rh);
+                lb2 = __builtin_amdgcn_logf(1.0f + rh);
+                lr1 = lb1 * kLn2f;
+                lr2 = lb2 * kLn2f;
+                an = nu * 1.44269504088896341f;   // al noa = nu
+                omr2 = (1.0f - rh) * (1.0f + rh);
+            } else {
+                lr1 = M<R>::lg((R)1 - rh);
+                lr2 = M<R>::lg((R)1 + rh);
+            }
             d1 = omb * omb * (R)(1.0 / 24.0);
             d2 = d1 * d1 * (R)(576.0 / 1920.0);
-            if constexpr (sizeof(R) == 4) xs.init(y[1]);
+            if constexpr (sizeof(R) == 4) xs.init(rh);
         }
         if (MODEL == MODEL_DYN_II) return case2_feasible(y, t_max);
         return true;
@@ -229,7 +239,7 @@ struct ModelEval {
             const R z = noa * Z;
             R zx;
             if constexpr (sizeof(R) == 4) {
-                zx = (fabsf(z) < (float)kZIsland) ? __builtin_amdgcn_rcpf((float)xs.eval((double)z))
+                zx = (fabsf(z) < (float)kZIsland) ? __builtin_amdgcn_rcpf(xs.eval(z))
                                                    : z * __builtin_amdgcn_rcpf(x_log_f32(z, rh, lr1, lr2));
             } else {
                 zx = M<R>::zx(z, rh, lr1, lr2);
@@ -258,55 +268,87 @@ __device__ __forceinline__ bool vol_ok(R sig) { return sig > (R)0 && sig < (R)__
 // fewer lanes than its points.
 template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE, int LPC = 1>
 __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
-                            double beta_fixed, double t_max, double *out, int sub = 0, int rsplit = 1) {
+                            double beta_fixed, double t_max, double *out, int sub = 0, int rsplit = 1,
+                            Row<R> r0 = Row<R>{}, bool have_r0 = false) {
     ModelEval<MODEL, FORMULA, R, BFREE> ev;
     if (!ev.init(y, beta_fixed, t_max)) return __builtin_inf();
     double acc = 0.0;
     bool bad = false;
     if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION && !BFREE && sizeof(R) == 4 && !WRITE) {
-        // float hot loop of the static z-form formulas: two points per step so
-        // that their dependency chains interleave, the next pair's LDS records
-        // requested before the current pair is computed, and one branch per
-        // pair into the double near-the-money series.
-        const float c1a2 = ev.c1a2, c2rna = ev.c2rna, c3n2 = ev.c3n2, noa = ev.noa, alf = ev.al;
+        // float hot loop of the static z-form formulas, two points per step so
+        // that their dependency chains interleave.  With zr = z - rho and
+        // q = sqrt(zr^2 + 1 - rho^2) (= sqrt(1 - 2 rho z + z^2)), x(z) / ln 2 is
+        // log2(q + zr) - log2(1 - rho) for zr >= 0 and log2(1 + rho) -
+        // log2(q - zr) for zr < 0 (rationalised as in x_log_f32), so the vol is
+        // (nu / ln 2) (P1 Z) corr / (x / ln 2); near the money, where that
+        // form cancels, al P1 corr (z / x) from the double series.  The
+        // maturity factor corr = 1 + T (c1a2 Q2 + c2rna Q1 + c3n2) takes its T
+        // from the row.
+        const float an = ev.an, noa = ev.noa, rh = ev.rh, lb1 = ev.lb1, lb2 = ev.lb2, omr2 = ev.omr2;
+        float k0 = 1.0f, k1 = 0.0f, k2 = 0.0f;
+        auto vol = [&](const Pt<R> &p, float &sg, bool &isl) {
+            const float z = noa * p.Z;
+            const float zr = z - rh;
+            const float q = __builtin_amdgcn_sqrtf(fmaf(zr, zr, omr2));
+            const float L = __builtin_amdgcn_logf(q + fabsf(zr));
+            const float xb = zr >= 0.0f ? L - lb1 : lb2 - L;
+            const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
+            sg = an * p.PZ * corr * __builtin_amdgcn_rcpf(xb);
+            isl = fabsf(z) < (float)kZIsland;
+        };
+        auto island = [&](const Pt<R> &p) {
+            const float z = noa * p.Z;
+            const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
+            return ev.al * p.P1 * corr * __builtin_amdgcn_rcpf(ev.xs.eval(z));
+        };
         auto pair = [&](const Pt<R> &pa, const Pt<R> &pb) {
-            const float za = noa * pa.Z, zb = noa * pb.Z;
-            float zxa = za * __builtin_amdgcn_rcpf(x_log_f32(za, ev.rh, ev.lr1, ev.lr2));
-            float zxb = zb * __builtin_amdgcn_rcpf(x_log_f32(zb, ev.rh, ev.lr1, ev.lr2));
-            const bool ia = fabsf(za) < (float)kZIsland, ib = fabsf(zb) < (float)kZIsland;
+            float sa, sb;
+            bool ia, ib;
+            vol(pa, sa, ia);
+            vol(pb, sb, ib);
             if (__builtin_expect(ia || ib, 0)) {
-                if (ia) zxa = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)za));
-                if (ib) zxb = __builtin_amdgcn_rcpf((float)ev.xs.eval((double)zb));
+                if (ia) sa = island(pa);
+                if (ib) sb = island(pb);
             }
-            const float ca = fmaf(fmaf(c1a2, pa.Q2, fmaf(c2rna, pa.Q1, c3n2)), pa.T, 1.0f);
-            const float cb = fmaf(fmaf(c1a2, pb.Q2, fmaf(c2rna, pb.Q1, c3n2)), pb.T, 1.0f);
-            const float sa = alf * pa.P1 * zxa * ca, sb = alf * pb.P1 * zxb * cb;
             bad |= !vol_ok(sa) || !vol_ok(sb);
             const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
             acc = fma(ea, ea, acc);
             acc = fma(eb, eb, acc);
         };
         auto single = [&](const Pt<R> &p) {
-            const float sig = ev.point(p);
-            bad |= !vol_ok(sig);
-            const double e = fma(-(double)sig, p.sw, p.tsw);
+            float sg;
+            bool is;
+            vol(p, sg, is);
+            if (is) sg = island(p);
+            bad |= !vol_ok(sg);
+            const double e = fma(-(double)sg, p.sw, p.tsw);
             acc = fma(e, e, acc);
         };
         for (int i = 0; i < n_mat; ++i) {
-            const Row<R> rw = rows[i];
+            const Row<R> rw = (i == 0 && have_r0) ? r0 : rows[i];
             int j = rw.p0 + sub;
             if (j >= rw.p1) continue;
-            // records loaded one pair ahead; reads past the row's end land in
-            // the next row or the spare records and are not used
+            k0 = fmaf(ev.c3n2, rw.T, 1.0f);
+            k1 = ev.c1a2 * rw.T;
+            k2 = ev.c2rna * rw.T;
+            // two pairs per step, each pair's records loaded while the other
+            // is computed (two register sets, no copies); reads past the
+            // row's end land in the next row or the spare records, unused
             const Pt<R> *pp = pts + j;
-            Pt<R> na = pp[0], nb = pp[LPC];
-            for (; j + LPC < rw.p1; j += 2 * LPC, pp += 2 * LPC) {
-                const Pt<R> pa = na, pb = nb;
-                na = pp[2 * LPC];
-                nb = pp[3 * LPC];
-                pair(pa, pb);
+            Pt<R> a0 = pp[0], b0 = pp[LPC];
+            for (; j + 3 * LPC < rw.p1; j += 4 * LPC, pp += 4 * LPC) {
+                const Pt<R> a1 = pp[2 * LPC], b1 = pp[3 * LPC];
+                pair(a0, b0);
+                a0 = pp[4 * LPC];
+                b0 = pp[5 * LPC];
+                pair(a1, b1);
             }
-            if (j < rw.p1) single(na);
+            if (j + LPC < rw.p1) {
+                pair(a0, b0);
+                if (j + 2 * LPC < rw.p1) single(pp[2 * LPC]);
+            } else if (j < rw.p1) {
+                single(a0);
+            }
         }
         return bad ? __builtin_inf() : acc;
     }

@@ -50,13 +50,14 @@ __device__ __forceinline__ bool metropolis_w(double fy, double fx, uint32_t w, d
 
 // Float proposal (float annealing mode): the same reflection and clamp as
 // propose_coord, on the float values the float objective sees.
+// Each reflection is a min (max) with the reflected value, which lies on the
+// far side of y exactly when y is outside the bound, so the result is the
+// same as the branches of propose_coord.
 __device__ __forceinline__ float propose_coord_f(float x, float u, float h, float lb, float ub) {
     float y = fmaf(h * fmaf(2.0f, u, -1.0f), ub - lb, x);
-    if (y > ub) y = ub - (y - ub);
-    if (y < lb) y = lb + (lb - y);
-    if (y > ub) y = ub;
-    if (y < lb) y = lb;
-    return y;
+    y = fminf(y, ub - (y - ub));
+    y = fmaxf(y, lb + (lb - y));
+    return fmaxf(fminf(y, ub), lb);
 }
 
 // Sum of a double over the LPC consecutive lanes of a lane group (LPC <= 16),
