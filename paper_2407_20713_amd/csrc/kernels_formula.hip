@@ -122,14 +122,14 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
         const double Tk = T0 * g;
         const int t1 = min((lev + 1) * L, n_iters);
         if (active) sa_level<NP, NB, LPC, R>(chain, sub, lev * L, t1, k0, k1, h, Tk, s_lb, s_ub, x, fx, bx, fb, nacc, f_of);
-        request_argmin<NP>(fx, chain, active, x, am, rq, wg_local, round++, cands, err);
+        if (!request_argmin<NP>(fx, chain, active, x, am, rq, wg_local, round++, cands, err)) return;
         fx = am.bf;
 #pragma unroll
         for (int k = 0; k < NP; ++k) x[k] = am.bx[k];
         __syncthreads();
     }
     // best-so-far over all chains of the request
-    request_argmin<NP>(fb, chain, active, bx, am, rq, wg_local, round++, cands, err);
+    if (!request_argmin<NP>(fb, chain, active, bx, am, rq, wg_local, round++, cands, err)) return;
     // accepted moves: workgroup sum, one integer atomic per workgroup
     unsigned long long a = (active && sub == 0) ? nacc : 0ull;
 #pragma unroll

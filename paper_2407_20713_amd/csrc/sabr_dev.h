@@ -73,11 +73,13 @@ struct ChainOut {
     double bx[kMaxPar];
 };
 
-struct alignas(128) Cand {   // level-end candidate of one workgroup (own cache line)
-    double f;
-    int32_t chain;
-    uint32_t tag;            // exchange round + 1 once f, chain and x are published
-    double x[kMaxPar];
+// Level-end candidate of one workgroup: f, chain and x as 32-bit words, each
+// stored in the low half of a 64-bit word whose high half is the exchange
+// round + 1.  A 64-bit atomic access is indivisible, so a reader that sees the
+// round in every word has the whole candidate of that round, with no fence.
+constexpr int kCandWords = 3 + 2 * kMaxPar;
+struct alignas(64) Cand {
+    uint64_t w[kCandWords];
 };
 
 // ---------------------------------------------------------------------------

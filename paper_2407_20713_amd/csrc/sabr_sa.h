@@ -171,7 +171,7 @@ struct ArgminSmem {
     int wid[16];
     double bf;
     int bid;
-    int pad;
+    int fail;   // a wait of the exchange timed out
     double bx[kMaxPar];
 };
 
@@ -179,13 +179,15 @@ struct ArgminSmem {
 // exchange candidates through device memory).  Afterwards every thread sees
 // the winner in s.bf / s.bx.  `round` counts exchanges; slots alternate
 // between two halves so that a fast workgroup can never overwrite a slot
-// another one has not read yet.  Each workgroup publishes its candidate with
-// a release store of the round's tag; the first wave of every workgroup
-// watches all the request's slots (lane w slot w) until their tags show the
-// round, then takes an acquire fence and reads them.
+// another one has not read yet (it publishes round r + 2 only after every
+// workgroup has published round r + 1, which each does after reading round
+// r).  The first wave of each workgroup publishes its candidate as tagged
+// words (lane k stores word k) and then watches the request's slots (lane w
+// slot w), reading every word of a slot at once until all show the round.  Returns false, with *err set, if a
+// slot did not show the round within the wait bound (the caller then ends).
 template <int NP>
-__device__ inline void request_argmin(double f, int chain, bool active, const double *x, ArgminSmem &s,
-                               const ReqDesc &rq, int wg_local, int round, Cand *cands, int32_t *err) {
+__device__ inline bool request_argmin(double f, int chain, bool active, const double *x, ArgminSmem &s,
+                                      const ReqDesc &rq, int wg_local, int round, Cand *cands, int32_t *err) {
     double wf = active ? f : __builtin_inf();
     int wid = active ? chain : 0x7fffffff;
     wave_argmin(wf, wid);
@@ -205,6 +207,7 @@ __device__ inline void request_argmin(double f, int chain, bool active, const do
             }
         s.bf = bf;
         s.bid = bid;
+        s.fail = 0;
     }
     __syncthreads();
     if (active && chain == s.bid) {
@@ -213,49 +216,65 @@ __device__ inline void request_argmin(double f, int chain, bool active, const do
     }
     __syncthreads();
     if (rq.n_wg > 1) {
+        constexpr int NW = 3 + 2 * NP;   // words of a candidate
         Cand *half = cands + rq.cand_off + (round & 1) * rq.n_wg;
-        const uint32_t tag = (uint32_t)round + 1u;
-        if (threadIdx.x == 0) {
-            Cand &c = half[wg_local];
-            c.f = s.bf;
-            c.chain = s.bid;
-            for (int k = 0; k < NP; ++k) c.x[k] = s.bx[k];
-            __hip_atomic_store(&c.tag, tag, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (threadIdx.x < 64) {
-            for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
-                int spins = 0;
-                while (__hip_atomic_load(&half[w].tag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != tag) {
-                    __builtin_amdgcn_s_sleep(1);
-                    if (++spins > (1 << 24)) {
-                        __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        break;
-                    }
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        // the first wave reads every candidate (with its x) at once and takes
-        // their argmin; the winning lane hands its x over
+        const uint32_t tag32 = (uint32_t)(round + 1);
+        const uint64_t tag = (uint64_t)tag32 << 32;
+        // words: f (low, high), chain, then x[i] (low, high)
+        auto word_of = [&](int k) -> uint32_t {
+            if (k == 2) return (uint32_t)s.bid;
+            const uint64_t b = __builtin_bit_cast(uint64_t, k < 2 ? s.bf : s.bx[k < 3 ? 0 : (k - 3) >> 1]);
+            const bool high = k < 2 ? k == 1 : ((k - 3) & 1) == 1;
+            return high ? (uint32_t)(b >> 32) : (uint32_t)b;
+        };
+        if (threadIdx.x < NW)
+            __hip_atomic_store(&half[wg_local].w[threadIdx.x], tag | word_of(threadIdx.x), __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
         if (threadIdx.x < 64) {
             double cf = __builtin_inf();
             int cid = 0x7fffffff;
             double cx[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k) cx[k] = 0.0;
+            bool timed_out = false;
             for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
-                const double fw = __hip_atomic_load(&half[w].f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const int iw = __hip_atomic_load(&half[w].chain, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                double xw[NP];
+                uint64_t *cw = half[w].w;
+                uint32_t pay[NW];
+                int spins = 0;
+                for (;;) {
+                    // every word in one trip: all loads issued before any is used
+                    uint64_t v[NW];
 #pragma unroll
-                for (int k = 0; k < NP; ++k)
-                    xw[k] = __hip_atomic_load(&half[w].x[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    for (int k = 0; k < NW; ++k)
+                        v[k] = __hip_atomic_load(&cw[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __builtin_amdgcn_sched_barrier(0);
+                    bool all = true;
+#pragma unroll
+                    for (int k = 0; k < NW; ++k) {
+                        pay[k] = (uint32_t)v[k];
+                        all &= (uint32_t)(v[k] >> 32) == tag32;
+                    }
+                    if (all) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if (++spins > (1 << 22)) {
+                        timed_out = true;
+                        break;
+                    }
+                }
+                if (timed_out) break;
+                const double fw = __builtin_bit_cast(double, ((uint64_t)pay[1] << 32) | pay[0]);
+                const int iw = (int)pay[2];
                 if (fw < cf || (fw == cf && iw < cid)) {
                     cf = fw;
                     cid = iw;
 #pragma unroll
-                    for (int k = 0; k < NP; ++k) cx[k] = xw[k];
+                    for (int k = 0; k < NP; ++k)
+                        cx[k] = __builtin_bit_cast(double, ((uint64_t)pay[4 + 2 * k] << 32) | pay[3 + 2 * k]);
                 }
+            }
+            if (timed_out) {
+                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s.fail = 1;
             }
             int key = cid;
             double kf = cf;
@@ -271,6 +290,7 @@ __device__ inline void request_argmin(double f, int chain, bool active, const do
         }
         __syncthreads();
     }
+    return s.fail == 0;
 }
 
 // ---------------------------------------------------------------------------
