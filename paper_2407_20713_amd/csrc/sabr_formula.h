@@ -11,7 +11,7 @@ template <typename R>
 struct alignas(16) Pt {
     R Z, PZ, Q1, Q2;      // beta fixed: z factor, P1 Z, (Kf)^-(1-b)/2, (Kf)^-(1-b)
     R P1, lfk, lkf, T;    // leading factor, ln(f/K), ln(Kf), maturity
-    double tsw, sw;       // market value times sqrt(weight), sqrt(weight)
+    R tsw, sw;            // market value times sqrt(weight), sqrt(weight)
 };
 template <typename R>
 struct alignas(16) Row {
@@ -76,8 +76,8 @@ __device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const Mat
         p.lfk = (R)P.lfk[g];
         p.lkf = (R)P.lkf[g];
         p.T = (R)Mt.T[P.row[g]];
-        p.sw = P.sw[g];
-        p.tsw = P.target[g] * p.sw;
+        p.sw = (R)P.sw[g];
+        p.tsw = (R)(P.target[g] * P.sw[g]);
         pts[j] = p;
     }
     for (int i = threadIdx.x; i < rq.n_mat; i += blockDim.x) {
@@ -272,7 +272,6 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
                             Row<R> r0 = Row<R>{}, bool have_r0 = false) {
     ModelEval<MODEL, FORMULA, R, BFREE> ev;
     if (!ev.init(y, beta_fixed, t_max)) return __builtin_inf();
-    double acc = 0.0;
     bool bad = false;
     if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION && !BFREE && sizeof(R) == 4 && !WRITE) {
         // float hot loop of the static z-form formulas, two points per step so
@@ -280,26 +279,28 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
         // q = sqrt(zr^2 + 1 - rho^2) (= sqrt(1 - 2 rho z + z^2)), x(z) / ln 2 is
         // log2(q + zr) - log2(1 - rho) for zr >= 0 and log2(1 + rho) -
         // log2(q - zr) for zr < 0 (rationalised as in x_log_f32), so the vol is
-        // (nu / ln 2) (P1 Z) corr / (x / ln 2); near the money, where that
-        // form cancels, al P1 corr (z / x) from the double series.  The
-        // maturity factor corr = 1 + T (c1a2 Q2 + c2rna Q1 + c3n2) takes its T
-        // from the row.
-        const float an = ev.an, noa = ev.noa, rh = ev.rh, lb1 = ev.lb1, lb2 = ev.lb2, omr2 = ev.omr2;
-        float k0 = 1.0f, k1 = 0.0f, k2 = 0.0f;
+        // (P1 Z) (nu / ln 2) corr / (x / ln 2); near the money, where that form
+        // cancels, al P1 corr (z / x) from the series.  The maturity factor
+        // corr = 1 + T (c1a2 Q2 + c2rna Q1 + c3n2) takes its T from the row;
+        // its coefficients carry the factor nu / ln 2.  Residuals and their
+        // squares are summed in float (the float vols bound the accuracy).
+        const float noa = ev.noa, rh = ev.rh, lb1 = ev.lb1, lb2 = ev.lb2, omr2 = ev.omr2;
+        // near the money: |z| = noa |Z| < kZIsland
+        const float zthr = (float)kZIsland * ev.al * __builtin_amdgcn_rcpf(ev.nu);
+        float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
+        float acc_a = 0.0f, acc_b = 0.0f;
         auto vol = [&](const Pt<R> &p, float &sg, bool &isl) {
-            const float z = noa * p.Z;
-            const float zr = z - rh;
+            const float zr = fmaf(noa, p.Z, -rh);
             const float q = __builtin_amdgcn_sqrtf(fmaf(zr, zr, omr2));
             const float L = __builtin_amdgcn_logf(q + fabsf(zr));
             const float xb = zr >= 0.0f ? L - lb1 : lb2 - L;
             const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
-            sg = an * p.PZ * corr * __builtin_amdgcn_rcpf(xb);
-            isl = fabsf(z) < (float)kZIsland;
+            sg = p.PZ * corr * __builtin_amdgcn_rcpf(xb);
+            isl = fabsf(p.Z) < zthr;
         };
         auto island = [&](const Pt<R> &p) {
-            const float z = noa * p.Z;
             const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
-            return ev.al * p.P1 * corr * __builtin_amdgcn_rcpf(ev.xs.eval(z));
+            return ev.al * __builtin_amdgcn_rcpf(ev.an) * p.P1 * corr * __builtin_amdgcn_rcpf(ev.xs.eval(noa * p.Z));
         };
         auto pair = [&](const Pt<R> &pa, const Pt<R> &pb) {
             float sa, sb;
@@ -311,9 +312,9 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
                 if (ib) sb = island(pb);
             }
             bad |= !vol_ok(sa) || !vol_ok(sb);
-            const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
-            acc = fma(ea, ea, acc);
-            acc = fma(eb, eb, acc);
+            const float ea = fmaf(-sa, pa.sw, pa.tsw), eb = fmaf(-sb, pb.sw, pb.tsw);
+            acc_a = fmaf(ea, ea, acc_a);
+            acc_b = fmaf(eb, eb, acc_b);
         };
         auto single = [&](const Pt<R> &p) {
             float sg;
@@ -321,16 +322,16 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
             vol(p, sg, is);
             if (is) sg = island(p);
             bad |= !vol_ok(sg);
-            const double e = fma(-(double)sg, p.sw, p.tsw);
-            acc = fma(e, e, acc);
+            const float e = fmaf(-sg, p.sw, p.tsw);
+            acc_a = fmaf(e, e, acc_a);
         };
         for (int i = 0; i < n_mat; ++i) {
             const Row<R> rw = (i == 0 && have_r0) ? r0 : rows[i];
             int j = rw.p0 + sub;
             if (j >= rw.p1) continue;
-            k0 = fmaf(ev.c3n2, rw.T, 1.0f);
-            k1 = ev.c1a2 * rw.T;
-            k2 = ev.c2rna * rw.T;
+            k0 = ev.an * fmaf(ev.c3n2, rw.T, 1.0f);
+            k1 = ev.an * (ev.c1a2 * rw.T);
+            k2 = ev.an * (ev.c2rna * rw.T);
             // two pairs per step, each pair's records loaded while the other
             // is computed (two register sets, no copies); reads past the
             // row's end land in the next row or the spare records, unused
@@ -350,14 +351,16 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
                 single(a0);
             }
         }
-        return bad ? __builtin_inf() : acc;
+        return bad ? __builtin_inf() : (double)(acc_a + acc_b);
     }
     const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
     const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
     // float: two points per step with their own partial sums (two independent
-    // dependency chains), added once at the end; double: one sum in point order
+    // dependency chains), added once at the end; residuals in float, their
+    // squares summed in double (so the sum hardly depends on how the points
+    // are split over lanes); double: one sum in point order
     constexpr bool kTwo = sizeof(R) == 4;
-    double acc2 = 0.0;
+    double acc1 = 0.0, acc2 = 0.0;
     for (int i = rsub; i < n_mat; i += RS) {
         const Row<R> rw = rows[i];
         ev.row(rw);
@@ -366,8 +369,8 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
             const Pt<R> pa = pts[j], pb = pts[j + PS];
             const R sa = ev.point(pa), sb = ev.point(pb);
             bad |= !vol_ok(sa) || !vol_ok(sb);
-            const double ea = fma(-(double)sa, pa.sw, pa.tsw), eb = fma(-(double)sb, pb.sw, pb.tsw);
-            acc = fma(ea, ea, acc);
+            const double ea = (double)fma(-sa, pa.sw, pa.tsw), eb = (double)fma(-sb, pb.sw, pb.tsw);
+            acc1 = fma(ea, ea, acc1);
             acc2 = fma(eb, eb, acc2);
             if (WRITE) {
                 out[j] = (double)sa;
@@ -378,13 +381,13 @@ __device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *row
             const Pt<R> p = pts[j];
             const R sig = ev.point(p);
             bad |= !vol_ok(sig);
-            const double e = fma(-(double)sig, p.sw, p.tsw);
-            acc = fma(e, e, acc);
+            const double e = (double)fma(-sig, p.sw, p.tsw);
+            acc1 = fma(e, e, acc1);
             if (WRITE) out[j] = (double)sig;
         }
     }
-    if constexpr (kTwo) acc = acc + acc2;
-    return bad ? __builtin_inf() : acc;
+    if constexpr (kTwo) acc1 = acc1 + acc2;
+    return bad ? __builtin_inf() : acc1;
 }
 
 }  // namespace sabr

@@ -112,6 +112,37 @@ def test_static_objective_fp32(S, ctx, oracle, formula):
     assert worst < 2e-5
 
 
+@pytest.mark.parametrize("formula", [0, 1])
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_static_objective_fp32_values(S, ctx, oracle, formula, weighting):
+    """FP32 objective values without model output (the annealing's float
+    loop: vols, residuals and their sum in float) against the oracle's FP64
+    objective, within what a vol error of delta = 2e-5 allows:
+    |f32 - f| <= sum_i (2 |e_i| delta + delta^2) w_i + 1e-6 f.  Ragged rows
+    and strikes at and next to the forward (the near-the-money series)."""
+    K0 = np.exp(np.linspace(-0.4, 0.5, 7))
+    K1 = 1.3 * np.exp(np.array([-1e-2, -1e-4, -1e-7, 0.0, 1e-7, 1e-4, 1e-2]))
+    K2 = np.exp(np.linspace(-0.7, 0.6, 30))
+    g = inputs.make_grid([0.1, 1.3, 6.0], [K0, K1, K2], f0=1.3)
+    m = omkt(oracle, g)
+    tgt = oracle.model_vols(m, oracle.STATIC, [0.25, -0.4, 0.7], 0.6, False, formula) + 2e-3
+    m.target = tgt
+    X = random_params(inputs.STATIC, 300, 61 + formula)
+    f, _ = S.sabr_objective_batch(ctx, S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.6), X,
+                                  formula=formula, weighting=weighting, precision=S.SABR_FP32)
+    w = np.ones_like(tgt) if weighting == 0 else 1.0 / tgt ** 2
+    delta, n_checked = 2e-5, 0
+    for i in range(len(X)):
+        ref_f = oracle.objective_formula(m, oracle.STATIC, X[i], 0.6, False, formula, weighting)
+        ref_v = oracle.model_vols(m, oracle.STATIC, X[i], 0.6, False, formula)
+        if not (np.isfinite(ref_f) and np.all(np.isfinite(ref_v)) and np.all((ref_v > 0.01) & (ref_v < 5))):
+            continue
+        tol = np.sum((2 * np.abs(tgt - ref_v) * delta + delta ** 2) * w) + 1e-6 * ref_f
+        assert abs(f[i] - ref_f) <= tol, (i, f[i], ref_f, tol)
+        n_checked += 1
+    assert n_checked > 100
+
+
 def test_static_near_the_money_island(S, ctx, oracle):
     """Strikes within 1e-7..1e-2 of the forward, where z/x(z) cancels."""
     K = 1.0 * np.exp(np.array([-1e-2, -1e-4, -1e-7, 0.0, 1e-7, 1e-4, 1e-2]))
