@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
     const int rsplit = rq.rsplit;
     const uint32_t k0 = rq.key0, k1 = rq.key1;
     const Row<R> r0 = rows[0];   // the first row's record, kept in registers
-    auto f_of = [&](const double *v) {
+    auto f_of = [&](const auto *v) {
         double part = objective<MODEL, FORMULA, R, BFREE, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub,
                                                                       rsplit, r0, true);
         return group_sum<LPC>(part);

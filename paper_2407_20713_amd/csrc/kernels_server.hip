@@ -75,7 +75,7 @@ __device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
     const bool active = chain < rq.n_chains;
     const int n_mat = rq.n_mat, L = rq.chain_len, n_iters = rq.n_iters;
     const double beta = rq.beta, tmax = rq.t_max;
-    auto f_of = [&](const double *v) {
+    auto f_of = [&](const auto *v) {
         double part = objective<MODEL, FORMULA, float, false, false, LPC>(v, pts, rows, n_mat, beta, tmax, nullptr, sub);
         part = group_sum<LPC>(part);
         return part;

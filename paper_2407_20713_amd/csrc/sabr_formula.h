@@ -138,7 +138,7 @@ __device__ __forceinline__ Quad<R> dynamic_block(R F1, R T, R al, R beta, R n1sq
 // on the vector alone (init), on the maturity row (row) and on the strike
 // (point), so that a lane can evaluate a whole grid (objective) or a single
 // point (polish).
-template <int MODEL, int FORMULA, typename R, bool BFREE>
+template <int MODEL, int FORMULA, typename R, bool BFREE, typename P = double>
 struct ModelEval {
     R al, rh, nu, beta, omb;
     R noa, c1a2, c2rna, c3n2, lr1, lr2, d1, d2;   // z-form static formulas
@@ -149,13 +149,13 @@ struct ModelEval {
     // six terms leave a truncation below 0.05^6 / 7 = 2.3e-9, under the float
     // rounding of the result
     XzSeries<float, 6> xs;
-    const double *y;
+    const P *y;   // parameter vector (double, or float in the float annealing)
 
     // Returns false for a case II vector outside rho(t) in [-1,1], nu(t) > 0.
-    __device__ __forceinline__ bool init(const double *y_, double beta_fixed, double t_max) {
+    __device__ __forceinline__ bool init(const P *y_, double beta_fixed, double t_max) {
         constexpr int NP = base_npar<MODEL>() + (BFREE ? 1 : 0);
         y = y_;
-        const double beta_d = BFREE ? y[NP - 1] : beta_fixed;
+        const double beta_d = BFREE ? (double)y[NP - 1] : beta_fixed;
         al = (R)y[0];
         rh = (R)y[1];
         nu = (R)y[2];
@@ -184,7 +184,16 @@ struct ModelEval {
             d2 = d1 * d1 * (R)(576.0 / 1920.0);
             if constexpr (sizeof(R) == 4) xs.init(rh);
         }
-        if (MODEL == MODEL_DYN_II) return case2_feasible(y, t_max);
+        if constexpr (MODEL == MODEL_DYN_II) {
+            if constexpr (sizeof(P) == 8) {
+                return case2_feasible(y, t_max);
+            } else {
+                double yd[9];
+#pragma unroll
+                for (int k = 0; k < 9; ++k) yd[k] = (double)y[k];
+                return case2_feasible(yd, t_max);
+            }
+        }
         return true;
     }
 
@@ -266,11 +275,11 @@ __device__ __forceinline__ bool vol_ok(R sig) { return sig > (R)0 && sig < (R)__
 // rows i = sub % rsplit (mod rsplit)) and the points of each row over the
 // remaining LPC / rsplit lanes, so that a row's integrals are computed by
 // fewer lanes than its points.
-template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE, int LPC = 1>
-__device__ double objective(const double *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
+template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE, int LPC = 1, typename P = double>
+__device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
                             double beta_fixed, double t_max, double *out, int sub = 0, int rsplit = 1,
                             Row<R> r0 = Row<R>{}, bool have_r0 = false) {
-    ModelEval<MODEL, FORMULA, R, BFREE> ev;
+    ModelEval<MODEL, FORMULA, R, BFREE, P> ev;
     if (!ev.init(y, beta_fixed, t_max)) return __builtin_inf();
     bool bad = false;
     if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION && !BFREE && sizeof(R) == 4 && !WRITE) {

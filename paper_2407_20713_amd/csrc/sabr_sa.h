@@ -49,15 +49,19 @@ __device__ __forceinline__ bool metropolis_w(double fy, double fx, uint32_t w, d
 }
 
 // Float proposal (float annealing mode): the same reflection and clamp as
-// propose_coord, on the float values the float objective sees.
-// Each reflection is a min (max) with the reflected value, which lies on the
-// far side of y exactly when y is outside the bound, so the result is the
-// same as the branches of propose_coord.
-__device__ __forceinline__ float propose_coord_f(float x, float u, float h, float lb, float ub) {
-    float y = fmaf(h * fmaf(2.0f, u, -1.0f), ub - lb, x);
+// propose_coord, on the float values the float objective sees.  The step is
+// t hw with hw = h (ub - lb) and t = 2u - 1 = (2 (w >> 8) + 1) 2^-24 - 1 for
+// the 24-bit uniform u = ((w >> 8) + 1/2) 2^-24: t is exact in float (an odd
+// multiple of 2^-24 below 1 in size), so one fma gives it.  Each reflection is
+// a min (max) with the reflected value, which lies on the far side of y
+// exactly when y is outside the bound, so the result is the same as the
+// branches of propose_coord; the clamp is a median of three.
+__device__ __forceinline__ float propose_coord_f(float x, uint32_t w, float hw, float lb, float ub) {
+    const float t = fmaf((float)(w >> 8), 0x1p-23f, 0x1p-24f - 1.0f);
+    float y = fmaf(t, hw, x);
     y = fminf(y, ub - (y - ub));
     y = fmaxf(y, lb + (lb - y));
-    return fmaxf(fminf(y, ub), lb);
+    return __builtin_amdgcn_fmed3f(y, lb, ub);
 }
 
 // Sum of a double over the LPC consecutive lanes of a lane group (LPC <= 16),
@@ -93,7 +97,20 @@ __device__ __forceinline__ void sa_level(int chain, int sub, int t_begin, int t_
                                          double h, double Tk, const double *s_lb, const double *s_ub, double *x,
                                          double &fx, double *bx, double &fb, unsigned long long &nacc, FOBJ f_of) {
     const float invTf = (float)(1.0 / Tk);
-    const float hf = (float)h;
+    // float mode keeps the chain's state in float through the level (every
+    // state it can reach is a float proposal, or the start point, which the
+    // float objective sees rounded anyway); x is updated at the end
+    float xf[NP], lbf[NP], ubf[NP], hw[NP];
+    bool moved = false;
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+            xf[c] = (float)x[c];
+            lbf[c] = (float)s_lb[c];
+            ubf[c] = (float)s_ub[c];
+            hw[c] = (float)h * (ubf[c] - lbf[c]);
+        }
+    }
     for (int t0 = t_begin; t0 < t_end; t0 += LPC) {
         uint4 wm[NB];
 #pragma unroll
@@ -119,28 +136,48 @@ __device__ __forceinline__ void sa_level(int chain, int sub, int t_begin, int t_
 #pragma unroll 1
         for (int k = 0; k < kn; ++k) {
             if (k + 1 < kn) fetch(k + 1, wn);
-            double y[NP];
+            if constexpr (sizeof(R) == 4) {
+                float y[NP];
 #pragma unroll
-            for (int c = 0; c < NP; ++c) {
-                if constexpr (sizeof(R) == 4)
-                    y[c] = (double)propose_coord_f((float)x[c], unit_u24f(w[c]), hf, (float)s_lb[c], (float)s_ub[c]);
-                else
-                    y[c] = propose_coord(x[c], unit_u32(w[c]), h, s_lb[c], s_ub[c]);
-            }
-            const double fy = f_of(y);
-            if (metropolis_w(fy, fx, w[NP], Tk, invTf)) {
+                for (int c = 0; c < NP; ++c) y[c] = propose_coord_f(xf[c], w[c], hw[c], lbf[c], ubf[c]);
+                const double fy = f_of(y);
+                if (metropolis_w(fy, fx, w[NP], Tk, invTf)) {
 #pragma unroll
-                for (int c = 0; c < NP; ++c) x[c] = y[c];
-                fx = fy;
-                ++nacc;
-                if (fy < fb) {
-                    fb = fy;
+                    for (int c = 0; c < NP; ++c) xf[c] = y[c];
+                    moved = true;
+                    fx = fy;
+                    ++nacc;
+                    if (fy < fb) {
+                        fb = fy;
 #pragma unroll
-                    for (int c = 0; c < NP; ++c) bx[c] = y[c];
+                        for (int c = 0; c < NP; ++c) bx[c] = (double)y[c];
+                    }
+                }
+            } else {
+                double y[NP];
+#pragma unroll
+                for (int c = 0; c < NP; ++c) y[c] = propose_coord(x[c], unit_u32(w[c]), h, s_lb[c], s_ub[c]);
+                const double fy = f_of(y);
+                if (metropolis_w(fy, fx, w[NP], Tk, invTf)) {
+#pragma unroll
+                    for (int c = 0; c < NP; ++c) x[c] = y[c];
+                    fx = fy;
+                    ++nacc;
+                    if (fy < fb) {
+                        fb = fy;
+#pragma unroll
+                        for (int c = 0; c < NP; ++c) bx[c] = y[c];
+                    }
                 }
             }
 #pragma unroll
             for (int i = 0; i < NW; ++i) w[i] = wn[i];
+        }
+    }
+    if constexpr (sizeof(R) == 4) {
+        if (moved) {
+#pragma unroll
+            for (int c = 0; c < NP; ++c) x[c] = (double)xf[c];
         }
     }
 }
