@@ -292,12 +292,14 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         // cancels, al P1 corr (z / x) from the series.  The maturity factor
         // corr = 1 + T (c1a2 Q2 + c2rna Q1 + c3n2) takes its T from the row;
         // its coefficients carry the factor nu / ln 2.  Residuals and their
-        // squares are summed in float (the float vols bound the accuracy).
+        // squares are summed in float (the float vols bound the accuracy).  A
+        // vol that is not finite and positive shows in the smallest vol or
+        // makes the sum infinite or NaN.
         const float noa = ev.noa, rh = ev.rh, lb1 = ev.lb1, lb2 = ev.lb2, omr2 = ev.omr2;
         // near the money: |z| = noa |Z| < kZIsland
         const float zthr = (float)kZIsland * ev.al * __builtin_amdgcn_rcpf(ev.nu);
         float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
-        float acc_a = 0.0f, acc_b = 0.0f;
+        float acc_a = 0.0f, acc_b = 0.0f, smin = __builtin_inff();
         auto vol = [&](const Pt<R> &p, float &sg, bool &isl) {
             const float zr = fmaf(noa, p.Z, -rh);
             const float q = __builtin_amdgcn_sqrtf(fmaf(zr, zr, omr2));
@@ -320,7 +322,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
                 if (ia) sa = island(pa);
                 if (ib) sb = island(pb);
             }
-            bad |= !vol_ok(sa) || !vol_ok(sb);
+            smin = fminf(smin, fminf(sa, sb));
             const float ea = fmaf(-sa, pa.sw, pa.tsw), eb = fmaf(-sb, pb.sw, pb.tsw);
             acc_a = fmaf(ea, ea, acc_a);
             acc_b = fmaf(eb, eb, acc_b);
@@ -330,7 +332,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             bool is;
             vol(p, sg, is);
             if (is) sg = island(p);
-            bad |= !vol_ok(sg);
+            smin = fminf(smin, sg);
             const float e = fmaf(-sg, p.sw, p.tsw);
             acc_a = fmaf(e, e, acc_a);
         };
@@ -343,24 +345,34 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             k2 = ev.an * (ev.c2rna * rw.T);
             // two pairs per step, each pair's records loaded while the other
             // is computed (two register sets, no copies); reads past the
-            // row's end land in the next row or the spare records, unused
+            // row's end land in the next row or the spare records, unused.
+            // The steps every lane of the group can take (the row is the same
+            // for the whole wave) run under one wave-wide count; the last
+            // one to four points of a lane follow.
+            static_assert(LPC <= 2, "the read-ahead stays within the spare point records");
+            const int nq = __builtin_amdgcn_readfirstlane(((rw.p1 - rw.p0) / LPC) / 4);
             const Pt<R> *pp = pts + j;
             Pt<R> a0 = pp[0], b0 = pp[LPC];
-            for (; j + 3 * LPC < rw.p1; j += 4 * LPC, pp += 4 * LPC) {
+            for (int q = 0; q < nq; ++q, pp += 4 * LPC) {
                 const Pt<R> a1 = pp[2 * LPC], b1 = pp[3 * LPC];
                 pair(a0, b0);
                 a0 = pp[4 * LPC];
                 b0 = pp[5 * LPC];
                 pair(a1, b1);
             }
+            j += 4 * LPC * nq;
             if (j + LPC < rw.p1) {
                 pair(a0, b0);
-                if (j + 2 * LPC < rw.p1) single(pp[2 * LPC]);
+                if (j + 3 * LPC < rw.p1)
+                    pair(pp[2 * LPC], pp[3 * LPC]);
+                else if (j + 2 * LPC < rw.p1)
+                    single(pp[2 * LPC]);
             } else if (j < rw.p1) {
                 single(a0);
             }
         }
-        return bad ? __builtin_inf() : (double)(acc_a + acc_b);
+        const float acc = acc_a + acc_b;
+        return (smin > 0.0f && acc < __builtin_inff()) ? (double)acc : __builtin_inf();
     }
     const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
     const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
