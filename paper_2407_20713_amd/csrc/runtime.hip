@@ -51,6 +51,7 @@ struct sabr_ctx {
     std::vector<EventPair> pool;
     int force_lpc = 0;      // SABR_LANES_PER_CHAIN overrides the choice (1, 2, 4, 8 or 16)
     int force_rsplit = 0;   // SABR_ROW_SPLIT overrides the row split of a lane group (1 .. 16)
+    int spin_limit = 1 << 22;   // SABR_EXCHANGE_SPINS: polls of a level-end slot before a wait fails
     int crn_variant = 0;    // SABR_CRN_VARIANT: Monte Carlo objective kernel layout (0 = production)
     // caller's device workspace (sabr_ctx_set_workspace): buffers are carved from it
     unsigned char *ws = nullptr;
@@ -650,6 +651,7 @@ int plan_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, GroupPla
         d.sched_off = (int)pl.sg.size();
         d.polish = q.sa.polish;
         d.rsplit = row_split(c, q, lpc);
+        d.spin_limit = c->spin_limit;
         d.key0 = (uint32_t)(q.sa.seed & 0xffffffffu);
         d.key1 = (uint32_t)(q.sa.seed >> 32);
         d.T0 = q.sa.T0;
@@ -1061,6 +1063,10 @@ int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx 
     if (const char *e = std::getenv("SABR_ROW_SPLIT")) {
         const int v = std::atoi(e);
         c->force_rsplit = (v == 1 || v == 2 || v == 4 || v == 8 || v == 16) ? v : 0;
+    }
+    if (const char *e = std::getenv("SABR_EXCHANGE_SPINS")) {
+        const int v = std::atoi(e);
+        c->spin_limit = (v >= 0 && v <= (1 << 22)) ? v : (1 << 22);
     }
     int smem = 0;
     hipDeviceGetAttribute(&smem, hipDeviceAttributeMaxSharedMemoryPerBlock, device);

@@ -40,7 +40,7 @@ struct ReqDesc {
     int32_t cand_off;     // first candidate slot (2 * n_wg slots)
     int32_t polish;
     int32_t rsplit;       // lanes per chain that split the maturity rows (divides the lane count)
-    int32_t pad_r;
+    int32_t spin_limit;   // polls of a level-end slot before the wait gives up
     uint32_t key0, key1;
     double beta;
     double T0;            // <= 0: f(x0)

@@ -279,6 +279,10 @@ __device__ inline bool request_argmin(double f, int chain, bool active, const do
                 uint32_t pay[NW];
                 int spins = 0;
                 for (;;) {
+                    if (spins++ >= rq.spin_limit) {
+                        timed_out = true;
+                        break;
+                    }
                     // every word in one trip: all loads issued before any is used
                     uint64_t v[NW];
 #pragma unroll
@@ -293,10 +297,6 @@ __device__ inline bool request_argmin(double f, int chain, bool active, const do
                     }
                     if (all) break;
                     __builtin_amdgcn_s_sleep(1);
-                    if (++spins > (1 << 22)) {
-                        timed_out = true;
-                        break;
-                    }
                 }
                 if (timed_out) break;
                 const double fw = __builtin_bit_cast(double, ((uint64_t)pay[1] << 32) | pay[0]);

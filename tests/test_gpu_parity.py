@@ -646,3 +646,19 @@ def test_prepared_batch_refuses_mc_and_invalid(S, ctx):
     with pytest.raises(S.SabrError) as e:
         S.sabr_batch_prepare(ctx, [bad])
     assert e.value.code == S.SABR_E_INVAL
+
+
+def test_exchange_wait_bound_reports_timeout(S, ctx, oracle):
+    """A level-end wait that gives up (forced from the host: a context whose
+    bound allows no poll at all) ends every workgroup at once and the call
+    returns SABR_E_TIMEOUT; the same request then runs normally."""
+    req, _, _, _ = smile_request(S, oracle, np.array([0.2, -0.3, 0.5]), 1e-4, S.SABR_FP32, 2048, 100, 7)
+    c = _ctx_with(S, {"SABR_EXCHANGE_SPINS": "0"})
+    try:
+        with pytest.raises(S.SabrError) as e:
+            S.sabr_calibrate(c, [req])
+        assert e.value.code == S.SABR_E_TIMEOUT
+    finally:
+        c.close()
+    r = S.sabr_calibrate(ctx, [req])[0]
+    assert r["status"] == 0 and np.isfinite(r["f"])
