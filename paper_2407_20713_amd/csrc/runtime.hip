@@ -666,7 +666,7 @@ int plan_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, GroupPla
         d.wg_first = (int)pl.wg_req.size();
         for (int w = 0; w < d.n_wg; ++w) pl.wg_req.push_back(r);
         d.cand_off = pl.cand_slots;
-        pl.cand_slots += 2 * d.n_wg;
+        pl.cand_slots += 2 * d.n_wg + 2;   // two halves of candidates, two result slots
         if (d.polish) pl.pol.push_back(r);
         pl.multi_wg |= d.n_wg > 1;
     }

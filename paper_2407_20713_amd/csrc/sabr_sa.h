@@ -210,6 +210,7 @@ struct ArgminSmem {
     int bid;
     int fail;   // a wait of the exchange timed out
     double bx[kMaxPar];
+    double wx[kWG / 64][kMaxPar];   // each wave's winner (exchange read by a whole workgroup)
 };
 
 // Level-end argmin over every chain of the request (workgroups of one request
@@ -219,9 +220,15 @@ struct ArgminSmem {
 // another one has not read yet (it publishes round r + 2 only after every
 // workgroup has published round r + 1, which each does after reading round
 // r).  The first wave of each workgroup publishes its candidate as tagged
-// words (lane k stores word k) and then watches the request's slots (lane w
-// slot w), reading every word of a slot at once until all show the round.  Returns false, with *err set, if a
-// slot did not show the round within the wait bound (the caller then ends).
+// words (lane k stores word k).  Up to 64 workgroups, the first wave of each
+// then watches the request's slots (lane w slot w), reading every word of a
+// slot at once until all show the round.  Beyond 64, the request's first
+// workgroup alone reads the slots (thread t slots t, t + 256, ...), takes the
+// argmin and publishes it in the round's result slot (two of them, by round
+// parity), which the other workgroups watch: the same result with traffic
+// linear, not quadratic, in the workgroups.  Returns false, with *err set,
+// if a slot did not show the round within the wait bound (the caller then
+// ends).
 template <int NP>
 __device__ inline bool request_argmin(double f, int chain, bool active, const double *x, ArgminSmem &s,
                                       const ReqDesc &rq, int wg_local, int round, Cand *cands, int32_t *err) {
@@ -264,49 +271,60 @@ __device__ inline bool request_argmin(double f, int chain, bool active, const do
             const bool high = k < 2 ? k == 1 : ((k - 3) & 1) == 1;
             return high ? (uint32_t)(b >> 32) : (uint32_t)b;
         };
+        // reads every word of a slot in one trip until all show the round
+        // (false if the wait bound ran out)
+        auto poll = [&](const Cand *slot, uint32_t *pay) -> bool {
+            for (int spins = 0; spins < rq.spin_limit; ++spins) {
+                uint64_t v[NW];
+#pragma unroll
+                for (int k = 0; k < NW; ++k)
+                    v[k] = __hip_atomic_load(&slot->w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_sched_barrier(0);
+                bool all = true;
+#pragma unroll
+                for (int k = 0; k < NW; ++k) {
+                    pay[k] = (uint32_t)v[k];
+                    all &= (uint32_t)(v[k] >> 32) == tag32;
+                }
+                if (all) return true;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            return false;
+        };
+        auto pay_f = [](const uint32_t *pay) { return __builtin_bit_cast(double, ((uint64_t)pay[1] << 32) | pay[0]); };
+        auto pay_x = [](const uint32_t *pay, int k) {
+            return __builtin_bit_cast(double, ((uint64_t)pay[4 + 2 * k] << 32) | pay[3 + 2 * k]);
+        };
         if (threadIdx.x < NW)
             __hip_atomic_store(&half[wg_local].w[threadIdx.x], tag | word_of(threadIdx.x), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        if (threadIdx.x < 64) {
+        // the lanes that read slots (the first wave, one slot each, for up to
+        // 64 workgroups; beyond that the first workgroup reads every slot with
+        // all its threads and publishes the winner in a result slot that the
+        // others read: two more trips, but traffic linear in the workgroups)
+        const bool direct = rq.n_wg <= 64;
+        const bool reader = direct ? threadIdx.x < 64 : wg_local == 0;
+        if (reader) {
+            const int stride = direct ? 64 : (int)blockDim.x;
             double cf = __builtin_inf();
             int cid = 0x7fffffff;
             double cx[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k) cx[k] = 0.0;
             bool timed_out = false;
-            for (int w = threadIdx.x; w < rq.n_wg; w += 64) {
-                uint64_t *cw = half[w].w;
+            for (int w = threadIdx.x; w < rq.n_wg; w += stride) {
                 uint32_t pay[NW];
-                int spins = 0;
-                for (;;) {
-                    if (spins++ >= rq.spin_limit) {
-                        timed_out = true;
-                        break;
-                    }
-                    // every word in one trip: all loads issued before any is used
-                    uint64_t v[NW];
-#pragma unroll
-                    for (int k = 0; k < NW; ++k)
-                        v[k] = __hip_atomic_load(&cw[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __builtin_amdgcn_sched_barrier(0);
-                    bool all = true;
-#pragma unroll
-                    for (int k = 0; k < NW; ++k) {
-                        pay[k] = (uint32_t)v[k];
-                        all &= (uint32_t)(v[k] >> 32) == tag32;
-                    }
-                    if (all) break;
-                    __builtin_amdgcn_s_sleep(1);
+                if (!poll(&half[w], pay)) {
+                    timed_out = true;
+                    break;
                 }
-                if (timed_out) break;
-                const double fw = __builtin_bit_cast(double, ((uint64_t)pay[1] << 32) | pay[0]);
+                const double fw = pay_f(pay);
                 const int iw = (int)pay[2];
                 if (fw < cf || (fw == cf && iw < cid)) {
                     cf = fw;
                     cid = iw;
 #pragma unroll
-                    for (int k = 0; k < NP; ++k)
-                        cx[k] = __builtin_bit_cast(double, ((uint64_t)pay[4 + 2 * k] << 32) | pay[3 + 2 * k]);
+                    for (int k = 0; k < NP; ++k) cx[k] = pay_x(pay, k);
                 }
             }
             if (timed_out) {
@@ -318,11 +336,45 @@ __device__ inline bool request_argmin(double f, int chain, bool active, const do
             wave_argmin(kf, key);
             const unsigned long long m = __ballot(cid == key && cf == kf);
             const int src = __ffsll((long long)m) - 1;
-            if (threadIdx.x == src) {
+            if (direct) {
+                if (threadIdx.x == src) {
 #pragma unroll
-                for (int k = 0; k < NP; ++k) s.bx[k] = cx[k];
-                s.bf = kf;
-                s.bid = key;
+                    for (int k = 0; k < NP; ++k) s.bx[k] = cx[k];
+                    s.bf = kf;
+                    s.bid = key;
+                }
+            } else {
+                // every wave's winner, then the workgroup's, then the result slot
+                const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                if (lane == src) {
+                    s.wf[wave] = kf;
+                    s.wid[wave] = key;
+#pragma unroll
+                    for (int k = 0; k < NP; ++k) s.wx[wave][k] = cx[k];
+                }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int bw = 0;
+                    for (int v = 1; v < (int)(blockDim.x >> 6); ++v)
+                        if (s.wf[v] < s.wf[bw] || (s.wf[v] == s.wf[bw] && s.wid[v] < s.wid[bw])) bw = v;
+                    s.bf = s.wf[bw];
+                    s.bid = s.wid[bw];
+                    for (int k = 0; k < NP; ++k) s.bx[k] = s.wx[bw][k];
+                }
+                __syncthreads();
+                if (threadIdx.x < NW)
+                    __hip_atomic_store(&cands[rq.cand_off + 2 * rq.n_wg + (round & 1)].w[threadIdx.x],
+                                       tag | word_of(threadIdx.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        } else if (!direct && threadIdx.x == 0) {
+            uint32_t pay[NW];
+            if (poll(&cands[rq.cand_off + 2 * rq.n_wg + (round & 1)], pay)) {
+                s.bf = pay_f(pay);
+                s.bid = (int)pay[2];
+                for (int k = 0; k < NP; ++k) s.bx[k] = pay_x(pay, k);
+            } else {
+                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                s.fail = 1;
             }
         }
         __syncthreads();

@@ -317,10 +317,12 @@ def smile_request(S, oracle, x_true, noise_sd, prec, n_chains, n_iters, seed, po
     return req, m, lb, ub
 
 
-@pytest.mark.parametrize("n_chains", [64, 600, 1300])
+@pytest.mark.parametrize("n_chains", [64, 600, 1300, 8500])
 def test_sa_fp64_matches_oracle_trajectory(S, ctx, oracle, n_chains):
     """FP64 mode takes the oracle's annealing decisions: same accepted-move
-    count and the same best point (600 chains span 3 workgroups, ragged)."""
+    count and the same best point (600 chains span 3 workgroups, ragged;
+    8500 span 67, past the 64 whose level-end slots one wave reads, so one
+    workgroup reads them all and hands out the winner)."""
     say("sa fp64 chains", n_chains)
     x_true = np.array([0.2, -0.3, 0.5])
     req, m, lb, ub = smile_request(S, oracle, x_true, 1e-4, S.SABR_FP64, n_chains, 200, 0x5AB10001)
@@ -648,11 +650,13 @@ def test_prepared_batch_refuses_mc_and_invalid(S, ctx):
     assert e.value.code == S.SABR_E_INVAL
 
 
-def test_exchange_wait_bound_reports_timeout(S, ctx, oracle):
+@pytest.mark.parametrize("n_chains", [2048, 8500])
+def test_exchange_wait_bound_reports_timeout(S, ctx, oracle, n_chains):
     """A level-end wait that gives up (forced from the host: a context whose
     bound allows no poll at all) ends every workgroup at once and the call
-    returns SABR_E_TIMEOUT; the same request then runs normally."""
-    req, _, _, _ = smile_request(S, oracle, np.array([0.2, -0.3, 0.5]), 1e-4, S.SABR_FP32, 2048, 100, 7)
+    returns SABR_E_TIMEOUT; the same request then runs normally (16 and 67
+    workgroups: both ways of reading the slots)."""
+    req, _, _, _ = smile_request(S, oracle, np.array([0.2, -0.3, 0.5]), 1e-4, S.SABR_FP32, n_chains, 100, 7)
     c = _ctx_with(S, {"SABR_EXCHANGE_SPINS": "0"})
     try:
         with pytest.raises(S.SabrError) as e:
