@@ -666,3 +666,42 @@ def test_exchange_wait_bound_reports_timeout(S, ctx, oracle, n_chains):
         c.close()
     r = S.sabr_calibrate(ctx, [req])[0]
     assert r["status"] == 0 and np.isfinite(r["f"])
+
+
+def test_surface_full_size_sampled(S, ctx, oracle):
+    """The benchmark's workload in its launch configuration (24 fits x 4096
+    chains x 20000 iterations, float annealing, FP64 polish, one prepared
+    batch): on sampled fits, the reported objective equals the oracle's FP64
+    objective at the reported parameters, the float objective before the
+    polish is no smaller than the polished one (within float accuracy), and
+    the noise-free truth is recovered."""
+    fits = inputs.surface_fits()
+    gens, lb, ub = inputs.surface_true_params(len(fits))
+    reqs, truths, mkts = [], [], []
+    for k, g in enumerate(fits):
+        beta = g.meta["beta"]
+        m = omkt(oracle, g)
+        while True:
+            x = inputs.draw_params(gens[k], lb, ub)
+            vol = oracle.model_vols(m, oracle.STATIC, x, beta)
+            if np.all(np.isfinite(vol)) and np.all(vol > 0):
+                break
+        m.target = vol
+        reqs.append(S.Request(S.Market.from_grid(g, target=vol), S.Problem(S.SABR_STATIC, beta, lb, ub),
+                              precision=S.SABR_FP32, n_chains=4096, n_iters=20000, chain_len=10,
+                              cooling=0.99 ** (1000.0 / 20000), seed=0x5AB20000 + k, polish=True))
+        truths.append(x)
+        mkts.append(m)
+    b = S.sabr_batch_prepare(ctx, reqs)
+    try:
+        res = S.sabr_batch_run(b)
+    finally:
+        S.sabr_batch_destroy(b)
+    for k in (0, 5, 11, 12, 17, 23):
+        r, m, beta = res[k], mkts[k], fits[k].meta["beta"]
+        ref_f = oracle.objective_formula(m, oracle.STATIC, r["x"], beta)
+        say("fit", k, "f", r["f"], "oracle", ref_f, "before polish", r["f_before_polish"])
+        assert r["status"] == 0
+        assert abs(r["f"] - ref_f) <= 1e-12 * ref_f + 1e-14 * math.sqrt(ref_f * np.sum(m.target ** 2)) + 1e-28
+        assert r["f_before_polish"] >= r["f"] - 1e-6 * r["f_before_polish"] - 1e-20
+        np.testing.assert_allclose(r["x"], truths[k], rtol=0, atol=1e-6)
