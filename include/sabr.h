@@ -154,7 +154,11 @@ typedef struct sabr_ctx sabr_ctx;
 /* Context on HIP device `device`.  hbm_budget_bytes caps the device memory
  * the library may hold at once (0: no cap).  stream is a hipStream_t (for
  * example PyTorch's current stream) or NULL for a stream of the library's
- * own.  Errors: SABR_E_INVAL (bad device), SABR_E_DEVICE. */
+ * own.  Errors: SABR_E_INVAL (bad device), SABR_E_DEVICE.
+ * Environment read here, for tuning and tests: SABR_LANES_PER_CHAIN and
+ * SABR_ROW_SPLIT (lane layout of the annealing kernel), SABR_CRN_VARIANT
+ * (layout of the Monte Carlo objective kernel), SABR_EXCHANGE_SPINS (polls
+ * of a level-end slot before the wait gives up; default 2^22). */
 int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx **out);
 void sabr_ctx_destroy(sabr_ctx *ctx);
 /* Text of the last error on this context (never NULL; "" when none). */
@@ -183,7 +187,9 @@ int sabr_ctx_timing(sabr_ctx *ctx, int reset, double *kernel_ms, int64_t *launch
  * annealing launch per (model, formula, precision) group; Monte Carlo
  * requests run one after the other.  out[n_req] receives one result per
  * request (out[r].status < 0 for a request that failed validation; the call
- * then returns SABR_E_INVAL without running anything). */
+ * then returns SABR_E_INVAL without running anything).  SABR_E_TIMEOUT: a
+ * wait between the workgroups of one request at a level end exceeded its
+ * bound (the launch ends early; no result is valid). */
 int sabr_calibrate(sabr_ctx *ctx, int32_t n_req, const sabr_request *reqs, sabr_result *out);
 
 /* Prepared batches (Section 5, Technique I): the same calibration as
