@@ -134,8 +134,7 @@ __device__ __forceinline__ double x_over_z_series(double z, double rho) {
 }
 
 // Coefficients c_n = P_n(rho) / (n + 1) of the same series, for evaluating it
-// at many z with one rho (Horner in z).  In float for the float bulk: the
-// terms fall off as 0.05^n, so the sum is accurate to a few float roundings.
+// at many z with one rho (Horner in z), in the precision T.
 template <typename T, int NT>
 struct XzSeries {
     T c[NT];

@@ -145,10 +145,11 @@ struct ModelEval {
     R an, lb1, lb2, omr2;                         // float hot loop: nu / ln 2, log2(1 -/+ rho), 1 - rho^2
     R F1;                                         // f^(1-beta) of the current row
     Quad<R> q;                                    // expansion / dynamic row block
-    // near-the-money x(z)/z (float bulk): |z| < 0.05 and |P_n(rho)| <= 1, so
-    // six terms leave a truncation below 0.05^6 / 7 = 2.3e-9, under the float
-    // rounding of the result
-    XzSeries<float, 6> xs;
+    // near-the-money x(z)/z (float bulk, evaluated in double where z/x(z)
+    // cancels): |z| < 0.05 and |P_n(rho)| <= 1, so six terms leave a
+    // truncation below 0.05^6 / 7 = 2.3e-9, under the float rounding of the
+    // result
+    XzSeries<double, 6> xs;
     const P *y;   // parameter vector (double, or float in the float annealing)
 
     // Returns false for a case II vector outside rho(t) in [-1,1], nu(t) > 0.
@@ -182,7 +183,7 @@ struct ModelEval {
             }
             d1 = omb * omb * (R)(1.0 / 24.0);
             d2 = d1 * d1 * (R)(576.0 / 1920.0);
-            if constexpr (sizeof(R) == 4) xs.init(rh);
+            if constexpr (sizeof(R) == 4) xs.init((double)y[1]);
         }
         if constexpr (MODEL == MODEL_DYN_II) {
             if constexpr (sizeof(P) == 8) {
@@ -224,6 +225,11 @@ struct ModelEval {
         }
     }
 
+    // z / x(z) for |z| < kZIsland (float bulk)
+    __device__ __forceinline__ float zx_near(float z) const {
+        return __builtin_amdgcn_rcpf((float)xs.eval((double)z));
+    }
+
     __device__ __forceinline__ R point(const Pt<R> &p) const {
         if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION) {
             R P1, Z, Q1, Q2;
@@ -248,8 +254,7 @@ struct ModelEval {
             const R z = noa * Z;
             R zx;
             if constexpr (sizeof(R) == 4) {
-                zx = (fabsf(z) < (float)kZIsland) ? __builtin_amdgcn_rcpf(xs.eval(z))
-                                                   : z * __builtin_amdgcn_rcpf(x_log_f32(z, rh, lr1, lr2));
+                zx = (fabsf(z) < (float)kZIsland) ? zx_near(z) : z * __builtin_amdgcn_rcpf(x_log_f32(z, rh, lr1, lr2));
             } else {
                 zx = M<R>::zx(z, rh, lr1, lr2);
             }
@@ -291,15 +296,16 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         // (P1 Z) (nu / ln 2) corr / (x / ln 2); near the money, where that form
         // cancels, al P1 corr (z / x) from the series.  The maturity factor
         // corr = 1 + T (c1a2 Q2 + c2rna Q1 + c3n2) takes its T from the row;
-        // its coefficients carry the factor nu / ln 2.  Residuals and their
-        // squares are summed in float (the float vols bound the accuracy).  A
-        // vol that is not finite and positive shows in the smallest vol or
-        // makes the sum infinite or NaN.
+        // its coefficients carry the factor nu / ln 2.  Residuals in float,
+        // their squares summed in double (the sums that decide the Metropolis
+        // test).  A vol that is not finite and positive shows in the smallest
+        // vol or makes the sum infinite or NaN.
         const float noa = ev.noa, rh = ev.rh, lb1 = ev.lb1, lb2 = ev.lb2, omr2 = ev.omr2;
         // near the money: |z| = noa |Z| < kZIsland
         const float zthr = (float)kZIsland * ev.al * __builtin_amdgcn_rcpf(ev.nu);
         float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
-        float acc_a = 0.0f, acc_b = 0.0f, smin = __builtin_inff();
+        double acc_a = 0.0, acc_b = 0.0;
+        float smin = __builtin_inff();
         auto vol = [&](const Pt<R> &p, float &sg, bool &isl) {
             const float zr = fmaf(noa, p.Z, -rh);
             const float q = __builtin_amdgcn_sqrtf(fmaf(zr, zr, omr2));
@@ -311,7 +317,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         };
         auto island = [&](const Pt<R> &p) {
             const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
-            return ev.al * __builtin_amdgcn_rcpf(ev.an) * p.P1 * corr * __builtin_amdgcn_rcpf(ev.xs.eval(noa * p.Z));
+            return ev.al * __builtin_amdgcn_rcpf(ev.an) * p.P1 * corr * ev.zx_near(noa * p.Z);
         };
         auto pair = [&](const Pt<R> &pa, const Pt<R> &pb) {
             float sa, sb;
@@ -324,8 +330,8 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             }
             smin = fminf(smin, fminf(sa, sb));
             const float ea = fmaf(-sa, pa.sw, pa.tsw), eb = fmaf(-sb, pb.sw, pb.tsw);
-            acc_a = fmaf(ea, ea, acc_a);
-            acc_b = fmaf(eb, eb, acc_b);
+            acc_a = fma((double)ea, (double)ea, acc_a);
+            acc_b = fma((double)eb, (double)eb, acc_b);
         };
         auto single = [&](const Pt<R> &p) {
             float sg;
@@ -334,7 +340,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             if (is) sg = island(p);
             smin = fminf(smin, sg);
             const float e = fmaf(-sg, p.sw, p.tsw);
-            acc_a = fmaf(e, e, acc_a);
+            acc_a = fma((double)e, (double)e, acc_a);
         };
         for (int i = 0; i < n_mat; ++i) {
             const Row<R> rw = (i == 0 && have_r0) ? r0 : rows[i];
@@ -371,8 +377,8 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
                 single(a0);
             }
         }
-        const float acc = acc_a + acc_b;
-        return (smin > 0.0f && acc < __builtin_inff()) ? (double)acc : __builtin_inf();
+        const double acc = acc_a + acc_b;
+        return (smin > 0.0f && acc < __builtin_inf()) ? acc : __builtin_inf();
     }
     const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
     const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
