@@ -145,11 +145,6 @@ struct ModelEval {
     R an, lb1, lb2, omr2;                         // float hot loop: nu / ln 2, log2(1 -/+ rho), 1 - rho^2
     R F1;                                         // f^(1-beta) of the current row
     Quad<R> q;                                    // expansion / dynamic row block
-    // near-the-money x(z)/z (float bulk, evaluated in double where z/x(z)
-    // cancels): |z| < 0.05 and |P_n(rho)| <= 1, so six terms leave a
-    // truncation below 0.05^6 / 7 = 2.3e-9, under the float rounding of the
-    // result
-    XzSeries<double, 6> xs;
     const P *y;   // parameter vector (double, or float in the float annealing)
 
     // Returns false for a case II vector outside rho(t) in [-1,1], nu(t) > 0.
@@ -183,7 +178,6 @@ struct ModelEval {
             }
             d1 = omb * omb * (R)(1.0 / 24.0);
             d2 = d1 * d1 * (R)(576.0 / 1920.0);
-            if constexpr (sizeof(R) == 4) xs.init((double)y[1]);
         }
         if constexpr (MODEL == MODEL_DYN_II) {
             if constexpr (sizeof(P) == 8) {
@@ -225,8 +219,14 @@ struct ModelEval {
         }
     }
 
-    // z / x(z) for |z| < kZIsland (float bulk)
+    // z / x(z) for |z| < kZIsland (float bulk), in double where the log form
+    // cancels: |z| < 0.05 and |P_n(rho)| <= 1, so six terms of the series
+    // leave a truncation below 0.05^6 / 7 = 2.3e-9, under the float rounding
+    // of the result.  z = 0 (the strike at the forward) is the limit 1.
     __device__ __forceinline__ float zx_near(float z) const {
+        if (z == 0.0f) return 1.0f;
+        XzSeries<double, 6> xs;
+        xs.init((double)y[1]);
         return __builtin_amdgcn_rcpf((float)xs.eval((double)z));
     }
 
