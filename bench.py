@@ -53,7 +53,7 @@ SA_FETCH_KIB, SA_WRITE_KIB = 1165160.25, 145633.3125
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.1587, 1.0
 SA_TRAFFIC_BYTES = (SA_FETCH_KIB * FETCH_SCALE + SA_WRITE_KIB * WRITE_SCALE) * 1024
 # False once sa_kernel has changed since the counters above were taken (traffic then null)
-SA_COUNTERS_CURRENT = True
+SA_COUNTERS_CURRENT = False
 SLOTS_SA_PER_ITER = 200
 
 

@@ -219,15 +219,23 @@ struct ModelEval {
         }
     }
 
-    // z / x(z) for |z| < kZIsland (float bulk), in double where the log form
-    // cancels: |z| < 0.05 and |P_n(rho)| <= 1, so six terms of the series
-    // leave a truncation below 0.05^6 / 7 = 2.3e-9, under the float rounding
-    // of the result.  z = 0 (the strike at the forward) is the limit 1.
+    // z / x(z) for |z| < kZIsland (float bulk), from the series where the log
+    // form cancels: x(z)/z = 1 + z (c1 + z (c2 + z (c3 + z (c4 + z c5)))),
+    // c_n = P_n(rho) / (n + 1).  |z| < 0.05 and |P_n(rho)| <= 1, so the six
+    // terms leave a truncation below 0.05^6 / 7 = 2.3e-9.  The outer two terms
+    // are formed in double; the inner part c2 + z (...), at most 0.05^2 of the
+    // sum, in float (its rounding then counts below 1e-10 of the sum).  z = 0
+    // (the strike at the forward) is the limit 1.
     __device__ __forceinline__ float zx_near(float z) const {
         if (z == 0.0f) return 1.0f;
-        XzSeries<double, 6> xs;
-        xs.init((double)y[1]);
-        return __builtin_amdgcn_rcpf((float)xs.eval((double)z));
+        const float p2 = fmaf(1.5f * rh, rh, -0.5f);
+        const float p3 = fmaf(5.0f / 3.0f * rh, p2, -2.0f / 3.0f * rh);
+        const float p4 = fmaf(7.0f / 4.0f * rh, p3, -0.75f * p2);
+        const float p5 = fmaf(9.0f / 5.0f * rh, p4, -0.8f * p3);
+        const float inner = fmaf(z, fmaf(z, fmaf(z, p5 * (1.0f / 6.0f), p4 * 0.2f), p3 * 0.25f), p2 * (1.0f / 3.0f));
+        const double zd = (double)z;
+        const double s = fma(zd, fma(zd, (double)inner, 0.5 * (double)y[1]), 1.0);
+        return __builtin_amdgcn_rcpf((float)s);
     }
 
     __device__ __forceinline__ R point(const Pt<R> &p) const {
