@@ -116,12 +116,12 @@ __global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, cons
 // Box-Muller for 64 chains.  Payoffs are summed per lane in LDS in float over
 // the paths of the block; partial sums go to device memory lane-contiguous.
 // ---------------------------------------------------------------------------
-template <int MODEL, int NPATH, bool LDSB>
+template <int MODEL, int NPATH, bool LDSB, bool DIRECT = false>
 __global__ void __launch_bounds__(64) mc_crn_kernel(McCrnDesc d, const double *Y, const int32_t *mat_steps,
                                                    const int32_t *offs, const double *K, float *part) {
     extern __shared__ unsigned char smem[];
-    crn_block<MODEL, NPATH, LDSB>(d, blockIdx.x / d.n_pblocks, blockIdx.x % d.n_pblocks, Y, mat_steps, offs, K,
-                                  part, smem);
+    crn_block<MODEL, NPATH, LDSB, DIRECT>(d, blockIdx.x / d.n_pblocks, blockIdx.x % d.n_pblocks, Y, mat_steps, offs,
+                                          K, part, smem);
 }
 
 // Model prices and squared errors: grid (tiles, options), 256 threads.
@@ -181,6 +181,14 @@ const void *mc_crn_kernel_ptr(int model, int variant) {
     if (model < 0 || model > 2 || variant < 0 || variant > 9) return nullptr;
     return tab[model][variant];
 }
+// one round of kCrnPaths paths per block, sums straight to HBM
+const void *mc_crn_direct_kernel_ptr(int model) {
+    static const void *tab[3] = {(const void *)mc_crn_kernel<MODEL_STATIC, kCrnPaths, kCrnLdsNormals, true>,
+                                 (const void *)mc_crn_kernel<MODEL_DYN_I, kCrnPaths, kCrnLdsNormals, true>,
+                                 (const void *)mc_crn_kernel<MODEL_DYN_II, kCrnPaths, kCrnLdsNormals, true>};
+    return (model < 0 || model > 2) ? nullptr : tab[model];
+}
+int mc_crn_direct_paths() { return kCrnPaths; }
 const void *mc_crn_prices_ptr() { return (const void *)mc_crn_prices; }
 const void *mc_crn_objective_ptr() { return (const void *)mc_crn_objective; }
 const void *mc_sa_step_ptr() { return (const void *)mc_sa_step; }
@@ -190,8 +198,8 @@ size_t mc_price_smem_bytes(bool fp32, int m_max, int n_obs) {
     const size_t st = (fp32 ? sizeof(StepC<float>) : sizeof(StepC<double>)) * m_max;
     return st + (rs * n_obs + 15) / 16 * 16 + 2 * 4 * sizeof(double) * n_obs;
 }
-size_t mc_crn_smem_bytes(int n_obs) {
-    return crn_normals_bytes() + sizeof(float) * (((n_obs + 3) / 4) * 4 + 64 * (size_t)n_obs);
+size_t mc_crn_smem_bytes(int n_obs, bool direct) {
+    return crn_normals_bytes() + sizeof(float) * (((n_obs + 3) / 4) * 4 + (direct ? 0 : 64 * (size_t)n_obs));
 }
 
 }  // namespace sabr

@@ -822,7 +822,27 @@ int upload_mc_grid(sabr_ctx *c, const sabr_market &m, int spy, int weighting, Mc
     return SABR_OK;
 }
 
-void crn_geometry(int64_t n_chains, int64_t n_paths, McCrnDesc &d) {
+// Path blocks of the common-random-number kernel.  Direct: one round of
+// paths (16) per block, each block's option sums written straight to
+// HBM (chosen while those partials stay within 4 GB and half the context's
+// budget or workspace); otherwise up to 256 paths per block summed in LDS
+// first.
+bool crn_direct(const sabr_ctx *c, int64_t n_chains, int64_t n_paths, int n_obs) {
+    if (c->crn_variant != 0) return false;
+    const int64_t tiles = (n_chains + 63) / 64;
+    const int64_t np = mc_crn_direct_paths();
+    const int64_t nb = (n_paths + np - 1) / np;
+    const double bytes = 4.0 * 64 * (double)tiles * n_obs * (double)nb;
+    return bytes <= 4294967296.0 && (c->budget == 0 || bytes <= 0.5 * (double)c->budget) &&
+           (!c->ws || bytes <= 0.5 * (double)c->ws_bytes);
+}
+
+void crn_geometry(int64_t n_chains, int64_t n_paths, McCrnDesc &d, bool direct) {
+    if (direct) {
+        d.paths_per_block = mc_crn_direct_paths();
+        d.n_pblocks = (int32_t)((n_paths + d.paths_per_block - 1) / d.paths_per_block);
+        return;
+    }
     const int64_t tiles = (n_chains + 63) / 64;
     int64_t nb = std::max<int64_t>(1, 4096 / tiles);
     int64_t ppb = (n_paths + nb - 1) / nb;
@@ -853,13 +873,14 @@ int mc_objective_device(sabr_ctx *c, const McGrid &g, int model, int n_par, int 
     d.key1 = (uint32_t)(mc.seed >> 32);
     d.model = model;
     d.t_max = g.t_max;
-    crn_geometry(n_x, mc.n_paths, d);
+    const bool direct = crn_direct(c, n_x, mc.n_paths, g.n_obs);
+    crn_geometry(n_x, mc.n_paths, d, direct);
     const int64_t tiles = (n_x + 63) / 64;
     void *part;
     int rc;
     if ((rc = get_buf(c, S_PART, sizeof(float) * (size_t)tiles * g.n_obs * d.n_pblocks * 64, &part))) return rc;
-    const void *fn = mc_crn_kernel_ptr(model, c->crn_variant);
-    const size_t smem = mc_crn_smem_bytes(g.n_obs);
+    const void *fn = direct ? mc_crn_direct_kernel_ptr(model) : mc_crn_kernel_ptr(model, c->crn_variant);
+    const size_t smem = mc_crn_smem_bytes(g.n_obs, direct);
     if ((rc = set_smem(c, fn, smem))) return rc;
     const int32_t *ms = g.msteps, *mo = g.moffs;
     const double *K = g.K;

@@ -55,11 +55,13 @@ size_t sa_smem_fixed_bytes();
 const void *mc_price_kernel_ptr(bool fp32);
 const void *mc_price_finalize_ptr();
 const void *mc_crn_kernel_ptr(int model, int variant);
+const void *mc_crn_direct_kernel_ptr(int model);
+int mc_crn_direct_paths();   // paths per block of the direct kernel
 const void *mc_crn_prices_ptr();
 const void *mc_crn_objective_ptr();
 const void *mc_sa_step_ptr();
 const void *mc_sa_final_ptr();
 size_t mc_price_smem_bytes(bool fp32, int m_max, int n_obs);
-size_t mc_crn_smem_bytes(int n_obs);
+size_t mc_crn_smem_bytes(int n_obs, bool direct = false);
 
 }  // namespace sabr

@@ -108,7 +108,10 @@ __device__ __forceinline__ StepC<float> step_coeffs_f(const float *xf, float t, 
 // normals of a step are made once per wave (lane q * LPP + j draws the
 // Philox block (path q, step pair j) and turns both of its pairs into
 // normals) and broadcast to all lanes; payoffs go to per-lane float sums in
-// LDS, one per option.
+// LDS, one per option.  With DIRECT the block is one round of NPATH paths,
+// so each option's sum over them is complete at its maturity and goes
+// straight to the partials in HBM: no LDS per option, which otherwise sets
+// the occupancy (n_obs x 64 floats per wave).
 // With LDSB the normals of a chunk go through a small LDS table (one
 // broadcast read per step and path) instead of lane reads into scalar
 // registers.
@@ -116,7 +119,7 @@ constexpr int kCrnPaths = 16;       // paths per lane of the production kernels
 constexpr bool kCrnLdsNormals = true;
 __host__ __device__ constexpr int crn_normals_bytes() { return 1024; }   // NPATH x CH float2 = 128 x 8 B (any NPATH)
 
-template <int MODEL, int NPATH = kCrnPaths, bool LDSB = kCrnLdsNormals>
+template <int MODEL, int NPATH = kCrnPaths, bool LDSB = kCrnLdsNormals, bool DIRECT = false>
 __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const double *Y, const int32_t *mat_steps,
                           const int32_t *offs, const double *K, float *part, unsigned char *smem) {
     constexpr int LPP = 64 / NPATH;          // lanes per path when drawing normals
@@ -126,7 +129,8 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
     float *acc = Ks + ((d.n_obs + 3) / 4) * 4;        // [n_obs][64]
     const int lane = threadIdx.x;
     for (int o = lane; o < d.n_obs; o += 64) Ks[o] = (float)K[o];
-    for (int o = 0; o < d.n_obs; ++o) acc[o * 64 + lane] = 0.0f;
+    if constexpr (!DIRECT)
+        for (int o = 0; o < d.n_obs; ++o) acc[o * 64 + lane] = 0.0f;
     const int64_t chain = (int64_t)tile * 64 + lane;
     const bool active = chain < d.n_chains;
     constexpr int NP = MODEL == MODEL_STATIC ? 3 : (MODEL == MODEL_DYN_I ? 5 : 9);
@@ -210,7 +214,10 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
                                 float pay = 0.0f;
 #pragma unroll
                                 for (int q = 0; q < NPATH; ++q) pay += fmaxf(F[q] - Ks[o], 0.0f);
-                                acc[o * 64 + lane] += pay;
+                                if constexpr (DIRECT)
+                                    part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = pay;
+                                else
+                                    acc[o * 64 + lane] += pay;
                             }
                             ++mi;
                             mnext = mi < d.n_mat ? mat_steps[mi] : -1;
@@ -221,8 +228,9 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
         }
     }
     // partial layout: [tile][obs][pblock][lane]
-    for (int o = 0; o < d.n_obs; ++o)
-        part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = acc[o * 64 + lane];
+    if constexpr (!DIRECT)
+        for (int o = 0; o < d.n_obs; ++o)
+            part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = acc[o * 64 + lane];
 }
 
 // Price of option o for the 64 chains of one tile from the path-block
