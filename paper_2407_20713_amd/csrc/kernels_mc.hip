@@ -116,11 +116,11 @@ __global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, cons
 // Box-Muller for 64 chains.  Payoffs are summed per lane in LDS in float over
 // the paths of the block; partial sums go to device memory lane-contiguous.
 // ---------------------------------------------------------------------------
-template <int MODEL, int NPATH, bool LDSB, bool DIRECT = false>
+template <int MODEL, int NPATH, bool LDSB, int ACC = ACC_LDS>
 __global__ void __launch_bounds__(64) mc_crn_kernel(McCrnDesc d, const double *Y, const int32_t *mat_steps,
                                                    const int32_t *offs, const double *K, float *part) {
     extern __shared__ unsigned char smem[];
-    crn_block<MODEL, NPATH, LDSB, DIRECT>(d, blockIdx.x / d.n_pblocks, blockIdx.x % d.n_pblocks, Y, mat_steps, offs,
+    crn_block<MODEL, NPATH, LDSB, ACC>(d, blockIdx.x / d.n_pblocks, blockIdx.x % d.n_pblocks, Y, mat_steps, offs,
                                           K, part, smem);
 }
 
@@ -183,9 +183,9 @@ const void *mc_crn_kernel_ptr(int model, int variant) {
 }
 // one round of kCrnPaths paths per block, sums straight to HBM
 const void *mc_crn_direct_kernel_ptr(int model) {
-    static const void *tab[3] = {(const void *)mc_crn_kernel<MODEL_STATIC, kCrnPaths, kCrnLdsNormals, true>,
-                                 (const void *)mc_crn_kernel<MODEL_DYN_I, kCrnPaths, kCrnLdsNormals, true>,
-                                 (const void *)mc_crn_kernel<MODEL_DYN_II, kCrnPaths, kCrnLdsNormals, true>};
+    static const void *tab[3] = {(const void *)mc_crn_kernel<MODEL_STATIC, kCrnPaths, kCrnLdsNormals, ACC_DIRECT>,
+                                 (const void *)mc_crn_kernel<MODEL_DYN_I, kCrnPaths, kCrnLdsNormals, ACC_DIRECT>,
+                                 (const void *)mc_crn_kernel<MODEL_DYN_II, kCrnPaths, kCrnLdsNormals, ACC_DIRECT>};
     return (model < 0 || model > 2) ? nullptr : tab[model];
 }
 int mc_crn_direct_paths() { return kCrnPaths; }

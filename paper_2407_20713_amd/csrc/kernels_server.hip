@@ -229,7 +229,8 @@ __global__ void __launch_bounds__(64) mc_slot_crn_kernel(SlotDev *slots, int cls
     extern __shared__ unsigned char smem[];
     McCrnDesc d = s.crn;
     if (s.iter < 0) d.n_chains = 1;   // f(x0) from Y[0] = x0
-    crn_block<MODEL_STATIC>(d, 0, blockIdx.x % kMcPBlocks, s.Y, s.msteps, s.offs, s.K, s.part, smem);
+    crn_block<MODEL_STATIC, kCrnPaths, kCrnLdsNormals, ACC_HBM>(d, 0, blockIdx.x % kMcPBlocks, s.Y, s.msteps, s.offs,
+                                                              s.K, s.part, smem);
 }
 
 // Prices and squared errors of the slot's options: block (slot, g) takes the

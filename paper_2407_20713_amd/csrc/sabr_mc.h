@@ -108,10 +108,12 @@ __device__ __forceinline__ StepC<float> step_coeffs_f(const float *xf, float t, 
 // normals of a step are made once per wave (lane q * LPP + j draws the
 // Philox block (path q, step pair j) and turns both of its pairs into
 // normals) and broadcast to all lanes; payoffs go to per-lane float sums in
-// LDS, one per option.  With DIRECT the block is one round of NPATH paths,
-// so each option's sum over them is complete at its maturity and goes
-// straight to the partials in HBM: no LDS per option, which otherwise sets
-// the occupancy (n_obs x 64 floats per wave).
+// LDS, one per option (ACC_LDS).  ACC_DIRECT: the block is one round of
+// NPATH paths, so each option's sum over them is complete at its maturity and
+// goes straight to the partials in HBM.  ACC_HBM: the block's rounds add
+// into the block's own partials in HBM (each lane its own words).  Both
+// leave LDS free of the per-option sums, which otherwise set the occupancy
+// (n_obs x 64 floats per wave).
 // With LDSB the normals of a chunk go through a small LDS table (one
 // broadcast read per step and path) instead of lane reads into scalar
 // registers.
@@ -119,7 +121,8 @@ constexpr int kCrnPaths = 16;       // paths per lane of the production kernels
 constexpr bool kCrnLdsNormals = true;
 __host__ __device__ constexpr int crn_normals_bytes() { return 1024; }   // NPATH x CH float2 = 128 x 8 B (any NPATH)
 
-template <int MODEL, int NPATH = kCrnPaths, bool LDSB = kCrnLdsNormals, bool DIRECT = false>
+enum { ACC_LDS = 0, ACC_DIRECT = 1, ACC_HBM = 2 };
+template <int MODEL, int NPATH = kCrnPaths, bool LDSB = kCrnLdsNormals, int ACC = ACC_LDS>
 __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const double *Y, const int32_t *mat_steps,
                           const int32_t *offs, const double *K, float *part, unsigned char *smem) {
     constexpr int LPP = 64 / NPATH;          // lanes per path when drawing normals
@@ -129,7 +132,7 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
     float *acc = Ks + ((d.n_obs + 3) / 4) * 4;        // [n_obs][64]
     const int lane = threadIdx.x;
     for (int o = lane; o < d.n_obs; o += 64) Ks[o] = (float)K[o];
-    if constexpr (!DIRECT)
+    if constexpr (ACC == ACC_LDS)
         for (int o = 0; o < d.n_obs; ++o) acc[o * 64 + lane] = 0.0f;
     const int64_t chain = (int64_t)tile * 64 + lane;
     const bool active = chain < d.n_chains;
@@ -152,6 +155,13 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
     __syncthreads();
     const int64_t p_begin = (int64_t)pb * d.paths_per_block;
     const int64_t p_end = min<int64_t>(p_begin + d.paths_per_block, d.n_paths);
+    if constexpr (ACC != ACC_LDS) {
+        // a block past the last path still owns its (zero) partial sums
+        if (p_begin >= p_end) {
+            for (int o = 0; o < d.n_obs; ++o) part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = 0.0f;
+            return;
+        }
+    }
     for (int64_t path = p_begin; path < p_end; path += NPATH) {
         const int n_live = (int)min<int64_t>(NPATH, p_end - path);
         // X: log2(F/f0), -inf once absorbed; Xc: X clamped at the absorption
@@ -214,10 +224,12 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
                                 float pay = 0.0f;
 #pragma unroll
                                 for (int q = 0; q < NPATH; ++q) pay += fmaxf(F[q] - Ks[o], 0.0f);
-                                if constexpr (DIRECT)
-                                    part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = pay;
-                                else
+                                if constexpr (ACC == ACC_LDS) {
                                     acc[o * 64 + lane] += pay;
+                                } else {
+                                    float *pp = part + (((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane;
+                                    *pp = (ACC == ACC_HBM && path != p_begin) ? *pp + pay : pay;
+                                }
                             }
                             ++mi;
                             mnext = mi < d.n_mat ? mat_steps[mi] : -1;
@@ -228,7 +240,7 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
         }
     }
     // partial layout: [tile][obs][pblock][lane]
-    if constexpr (!DIRECT)
+    if constexpr (ACC == ACC_LDS)
         for (int o = 0; o < d.n_obs; ++o)
             part[(((size_t)tile * d.n_obs + o) * d.n_pblocks + pb) * 64 + lane] = acc[o * 64 + lane];
 }

@@ -429,7 +429,7 @@ int capture_graph(sabr_server *s) {
             void *a2[] = {&ds, &cls};
             ok = ok && hipStreamWaitEvent(s->stream_cls[c], s->ev_fork, 0) == hipSuccess;
             ok = ok && hipLaunchKernel(mc_slot_crn_kernel_ptr(), dim3(nmc * kMcPBlocks), dim3(64), a2,
-                                       mc_crn_smem_bytes(mc_class_obs(c)), s->stream_cls[c]) == hipSuccess;
+                                       mc_crn_smem_bytes(mc_class_obs(c), true), s->stream_cls[c]) == hipSuccess;
             ok = ok && hipEventRecord(s->ev_join[c], s->stream_cls[c]) == hipSuccess;
             ok = ok && hipStreamWaitEvent(s->stream_mc, s->ev_join[c], 0) == hipSuccess;
         }
@@ -649,7 +649,7 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
     ok = ok && hipFuncSetAttribute(sa_slot_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm) == hipSuccess;
     ok = ok && hipFuncSetAttribute(slot_polish_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)slot_polish_smem_bytes()) == hipSuccess;
-    const size_t msm = mc_crn_smem_bytes(kSlotMaxMcObs);
+    const size_t msm = mc_crn_smem_bytes(kSlotMaxMcObs, true);
     ok = ok && hipFuncSetAttribute(mc_slot_crn_kernel_ptr(), hipFuncAttributeMaxDynamicSharedMemorySize, (int)msm) == hipSuccess;
     if (!ok || capture_graph(s) != SABR_OK) {
         hipGetLastError();
