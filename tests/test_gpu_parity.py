@@ -284,10 +284,16 @@ def test_mc_price_printed_case_full_size(S, ctx):
         assert abs(p[0] - printed) < 3 * math.sqrt(2) * se[0], (name, p, se)
 
 
+@pytest.mark.parametrize("layout", ["direct", "lds"])
 @pytest.mark.parametrize("model", [inputs.STATIC, inputs.DYN_I])
-def test_mc_objective_crn_parity(S, ctx, oracle, model):
+def test_mc_objective_crn_parity(S, ctx, oracle, model, layout):
     """Monte Carlo objective of 70 parameter vectors (two chain tiles, ragged)
-    on common paths equals the oracle's prices on the same normals."""
+    on common paths equals the oracle's prices on the same normals: with the
+    path-block sums written straight to device memory (the default here) and
+    with blocks of several rounds summed in LDS first (the layout taken when
+    the direct partials would not fit; forced by a kernel-layout override)."""
+    if layout == "lds":
+        ctx = _ctx_with(S, {"SABR_CRN_VARIANT": "9"})
     g = inputs.make_grid([0.25, 0.75], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0, disc=[0.995, 0.985])
     m = omkt(oracle, g)
     xt = [0.2, -0.3, 0.5] if model == inputs.STATIC else [0.2, -0.3, 0.5, 0.4, 0.6]
@@ -302,6 +308,30 @@ def test_mc_objective_crn_parity(S, ctx, oracle, model):
         np.testing.assert_allclose(mod[i], ref, rtol=5e-5, atol=1e-7)
         rf = oracle.objective_mc(m, model, X[i], 0.7, 1500, 250, 99)
         assert abs(f[i] - rf) <= 1e-3 * rf + 1e-8
+
+
+def test_mc_objective_lds_rounds_match_direct(S, ctx, oracle):
+    """3000 parameter vectors (47 chain tiles): the LDS layout then takes 87
+    path blocks of 18 paths (a full round of 16 and a partial one summed in
+    LDS); its prices match the oracle on sampled vectors and the direct
+    layout's on all of them."""
+    g = inputs.make_grid([0.25, 0.75], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0, disc=[0.995, 0.985])
+    m = omkt(oracle, g)
+    tgt, _ = oracle.mc_prices(m, inputs.STATIC, [0.2, -0.3, 0.5], 0.7, 1500, 250, 77)
+    X = random_params(inputs.STATIC, 3000, 53)
+    args = dict(kind=S.SABR_OBJ_MC, precision=S.SABR_FP32, n_paths=1500, steps_per_year=250, mc_seed=77,
+                want_model=True)
+    mk, pb = S.Market.from_grid(g, target=tgt), S.Problem(inputs.STATIC, 0.7)
+    _, mod_direct = S.sabr_objective_batch(ctx, mk, pb, X, **args)
+    c = _ctx_with(S, {"SABR_CRN_VARIANT": "9"})
+    try:
+        _, mod_lds = S.sabr_objective_batch(c, mk, pb, X, **args)
+    finally:
+        c.close()
+    np.testing.assert_allclose(mod_lds, mod_direct, rtol=5e-5, atol=1e-7)
+    for i in (0, 1, 63, 64, 1500, 2999):
+        ref, _ = oracle.mc_prices(m, inputs.STATIC, X[i], 0.7, 1500, 250, 77)
+        np.testing.assert_allclose(mod_lds[i], ref, rtol=5e-5, atol=1e-7)
 
 
 # --- annealing -----------------------------------------------------------------------------
