@@ -9,9 +9,9 @@
  * or do not exist (case II eta_2^2).
  *
  * Pinned by tests/test_oracle_pins.py against closed forms, limits, printed
- * values and brute force.  Parity unpinned: the case II asymptotic vols
- * (the paper prints none; only internal identities and quadrature
- * convergence cover them).
+ * values and brute force.  The case II integrals are pinned against the
+ * closed forms of Appendix A; the paper prints no case II vols to compare
+ * end to end.
  *
  * Build: gcc -O2 -std=c11 -ffp-contract=off -fPIC -shared (no -ffast-math),
  * so that the annealing arithmetic is evaluated exactly as written.

@@ -233,6 +233,118 @@ def test_case2_integrals_against_scipy(oracle, p):
     np.testing.assert_allclose(got, ref, rtol=1e-10)
 
 
+# Appendix A prints case II closed forms for nu1^2, nu2^2 and eta1, and the
+# inner integral I(s) = int_0^s nu(u) rho(u) du inside eta2^2 (which it
+# leaves to quadrature).  They are a derivation independent of the oracle's
+# (which integrates the exponential-polynomial products term by term and by
+# Gauss-Kronrod).  Reading: the b^5 d_nu q_rho term of the printed I(s)
+# carries a stray trailing factor 6; with factor 1 the printed expression
+# differentiates to nu(s) rho(s) exactly (its e^{(a+b)s} coefficients then
+# sum to b^2 (a+b)^3, as the d_nu q_rho u e^{-au} part of the integrand
+# requires), with 6 it does not.
+def _appendix_nu1sq(T, nu0, b, dn, qn):
+    e2 = math.exp(-2 * b * T)
+    e1 = math.exp(b * T)
+    br = (9 * qn ** 2 + 6 * b ** 4 * nu0 * (4 * dn + nu0) * T ** 2 + 4 * b ** 5 * dn ** 2 * T ** 3
+          + 9 * b * qn * (16 * dn + nu0 - qn * T)
+          + 6 * b ** 3 * T * (-nu0 * (8 * dn + nu0) + (4 * dn + nu0) * qn * T)
+          + 3 * b ** 2 * (nu0 * (16 * dn + nu0) - 4 * (8 * dn + nu0) * qn * T + qn ** 2 * T ** 2)
+          - 3 * e2 * (3 * qn ** 2 + 3 * b * qn * (16 * dn * e1 + nu0 + qn * T)
+                      + b ** 2 * (nu0 + qn * T) * (16 * dn * e1 + nu0 + qn * T)))
+    return br / (4 * b ** 5 * T ** 3)
+
+
+def _appendix_nu2sq(T, nu0, b, dn, qn):
+    e1 = math.exp(b * T)
+    v = nu0 + qn * T
+    br = (18 * qn ** 2 + 6 * b ** 3 * T * v ** 2 + 6 * b ** 2 * v * (nu0 + 3 * qn * T)
+          + 9 * b * qn * (2 * nu0 + 3 * qn * T)
+          + e1 ** 2 * (-18 * qn ** 2 + 6 * b ** 3 * nu0 * (8 * dn + nu0) * T + 4 * b ** 5 * dn ** 2 * T ** 3
+                       + 9 * b * qn * (-32 * dn - 2 * nu0 + qn * T)
+                       + 6 * b ** 2 * (-nu0 * (16 * dn + nu0) + 2 * (8 * dn + nu0) * qn * T))
+          + 48 * b * dn * e1 * (6 * qn + b * (nu0 * (2 + b * T) + qn * T * (4 + b * T))))
+    return math.exp(-2 * b * T) * br / (4 * b ** 5 * T ** 3)
+
+
+def _appendix_eta1(T, rho0, nu0, a, b, dr, dn, qr, qn):
+    s4 = (a + b) ** 4
+    ea, eb, eab = math.exp(a * T), math.exp(b * T), math.exp((a + b) * T)
+    vn, vr = nu0 + qn * T, rho0 + qr * T
+    head = (-2 * dn * qr / a ** 3 - 2 * dr * qn / b ** 3 - 6 * qr * qn / s4 + dr * nu0 * T / b
+            + dn * rho0 * T / a + (a ** 3 + b ** 3) * nu0 * rho0 * T / s4
+            + dn * (-rho0 + qr * T) / a ** 2 + dr * (-nu0 + qn * T) / b ** 2
+            + a ** 2 * (-nu0 * rho0 + nu0 * qr * T + qn * rho0 * T) / s4
+            - 2 * a * (nu0 * qr + qn * (rho0 - qr * T)) / s4
+            + b * (-2 * nu0 * (qr + a * rho0) + a * nu0 * (2 * qr + 3 * a * rho0) * T
+                   + 2 * qn * (qr * T + rho0 * (-1 + a * T))) / s4
+            + b ** 2 * (qn * rho0 * T + nu0 * (qr * T + rho0 * (-1 + 3 * a * T))) / s4)
+    tail = (4 * b ** 7 * dn * eb * qr + 8 * a ** 2 * b ** 5 * dn * eb * (b * rho0 + qr * (3 + b * T))
+            + 2 * a * b ** 6 * dn * eb * (b * rho0 + qr * (8 + b * T))
+            + (a ** 7 + 4 * a ** 6 * b) * dr * ea * (4 * qn + b ** 3 * dn * eb * T ** 2 + 2 * b * vn)
+            + 2 * a ** 5 * b ** 2 * (12 * dr * ea * qn + 3 * b ** 3 * dr * dn * eab * T ** 2 + 6 * b * dr * ea * vn
+                                     + b * vr * (dn * eb + vn))
+            + 4 * a ** 4 * b ** 3 * (dn * eb * qr + nu0 * qr + 4 * dr * ea * qn + qn * rho0 + 2 * qr * qn * T
+                                     + b ** 3 * dr * dn * eab * T ** 2 + 2 * b * dr * ea * vn
+                                     + b * vr * (2 * dn * eb + vn))
+            + a ** 3 * b ** 3 * (12 * qr * qn + b ** 4 * dr * dn * eab * T ** 2
+                                 + 4 * b * (4 * dn * eb * qr + nu0 * qr + qn * (dr * ea + rho0 + 2 * qr * T))
+                                 + 2 * b ** 2 * (dr * ea * vn + vr * (6 * dn * eb + vn))))
+    return 2 / T ** 2 * (head + math.exp(-(a + b) * T) * tail / (2 * a ** 3 * b ** 3 * s4))
+
+
+def _appendix_inner(s, rho0, nu0, a, b, dr, dn, qr, qn):
+    ea, eb, eab = math.exp(a * s), math.exp(b * s), math.exp((a + b) * s)
+    vn, vr = nu0 + qn * s, rho0 + qr * s
+    br = (b ** 5 * dn * eb * (-1 + ea) * qr
+          - a * b ** 4 * dn * eb * (3 * qr + b * rho0 - ea * (3 * qr + b * rho0) + b * qr * s)
+          + a ** 5 * dr * ea * (-qn - b * vn + eb * (qn + b * (nu0 + b * dn * s)))
+          + a ** 3 * b ** 2 * (-qn * (3 * dr * ea + rho0)
+                               + eab * ((dn + nu0) * qr + qn * (3 * dr + rho0)
+                                        + b * (3 * dr * nu0 + 3 * dn * rho0 + 2 * nu0 * rho0) + 3 * b ** 2 * dr * dn * s)
+                               - dn * eb * (qr + 3 * b * rho0 + 3 * b * qr * s) - qr * (nu0 + 2 * qn * s)
+                               - b * vn * (3 * dr * ea + 2 * vr))
+          + a ** 2 * b ** 2 * (-2 * qr * qn
+                               + eab * (2 * qr * qn + b ** 2 * (3 * dn * rho0 + nu0 * (dr + rho0))
+                                        + b * ((3 * dn + nu0) * qr + qn * (dr + rho0)) + b ** 3 * dr * dn * s)
+                               - 3 * b * dn * eb * (qr + b * rho0 + b * qr * s) - b ** 2 * (dr * ea + vr) * vn
+                               - b * (nu0 * qr + qn * (dr * ea + rho0 + 2 * qr * s)))
+          + a ** 4 * b * (eab * (3 * b * dr * nu0 + 3 * dr * qn + b * (dn + nu0) * rho0 + 3 * b ** 2 * dr * dn * s)
+                          - b * vr * (dn * eb + vn) - 3 * dr * ea * (qn + b * vn)))
+    return math.exp(-(a + b) * s) * br / (a ** 2 * b ** 2 * (a + b) ** 3)
+
+
+@pytest.mark.parametrize("p", [(-0.4, 0.6, 0.3, 0.5, 0.1, -0.05, 0.2, 0.3),
+                               (-0.964678, 1.285129, 0.7, 2.059560, 0.101632, -0.086294, -0.3, 1.302296),
+                               (0.5, 0.3, 1.9, 0.4, -0.2, 0.15, 0.6, -0.1)])
+@pytest.mark.parametrize("T", [1.0, 2.5, 7.0])
+def test_case2_integrals_match_appendix_closed_forms(oracle, p, T):
+    """Case II integrals (eq. "el_fun_3" in eq. "integrales_SABRd") equal the
+    closed forms printed in Appendix A: nu1^2, nu2^2 and eta1 directly, eta2^2
+    through the printed inner integral I(s) and the order swap
+    12/T^4 int_0^T (T - s) I(s)^2 ds."""
+    rho0, nu0, a, b, dr, dn, qr, qn = p
+    got = oracle.quad_integrals(oracle.DYN_II, T, rho0, nu0, a, b, dr, dn, qr, qn)
+    e2 = 12 / T ** 4 * si.quad(lambda s: (T - s) * _appendix_inner(s, *p) ** 2, 0, T,
+                               epsabs=0, epsrel=1e-13, limit=200)[0]
+    want = [_appendix_nu1sq(T, nu0, b, dn, qn), _appendix_nu2sq(T, nu0, b, dn, qn),
+            _appendix_eta1(T, *p), e2]
+    np.testing.assert_allclose(got, want, rtol=1e-11)
+
+
+def test_appendix_inner_integral_is_the_antiderivative():
+    """The printed I(s) (with the factor reading above) vanishes at 0 and its
+    derivative is nu(s) rho(s) of eq. "el_fun_3": this pins the reading, not
+    the oracle."""
+    p = (-0.4, 0.6, 0.3, 0.5, 0.1, -0.05, 0.2, 0.3)
+    rho0, nu0, a, b, dr, dn, qr, qn = p
+    assert abs(_appendix_inner(0.0, *p)) < 1e-15
+    for s in (0.2, 1.0, 3.0):
+        h = 1e-5
+        d = (_appendix_inner(s + h, *p) - _appendix_inner(s - h, *p)) / (2 * h)
+        nr = ((nu0 + qn * s) * math.exp(-b * s) + dn) * ((rho0 + qr * s) * math.exp(-a * s) + dr)
+        assert d == pytest.approx(nr, rel=1e-8)
+
+
 def _golden_vols():
     params, rows = {}, []
     with open(os.path.join(GOLDEN, "dsabr_case1_printed_vols.txt")) as fh:
