@@ -307,13 +307,23 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         // its coefficients carry the factor nu / ln 2.  Residuals in float,
         // their squares summed in double (the sums that decide the Metropolis
         // test).  A vol that is not finite and positive shows in the smallest
-        // vol or makes the sum infinite or NaN.
+        // vol or makes the sum infinite or NaN.  The smallest vol is tracked
+        // on the vols' bit patterns as signed integers: for non-negative
+        // floats that order is the float order, and every float with its sign
+        // bit set (negative, -0, negative NaN) compares below +0, so `> 0`
+        // holds exactly when each vol is a positive number, +inf or a NaN
+        // with the sign bit clear; those last two make the sum infinite or
+        // NaN.  (An integer minimum needs no NaN canonicalisation.)
         const float noa = ev.noa, rh = ev.rh, lb1 = ev.lb1, lb2 = ev.lb2, omr2 = ev.omr2;
         // near the money: |z| = noa |Z| < kZIsland
-        const float zthr = (float)kZIsland * ev.al * __builtin_amdgcn_rcpf(ev.nu);
+        // al / nu, from one hardware reciprocal: the island bound and the
+        // island's scale al / an = (al / nu) ln 2 both derive from it
+        const float aln = ev.al * __builtin_amdgcn_rcpf(ev.nu);
+        const float zthr = (float)kZIsland * aln;
+        const float iscale = aln * 0.693147180559945309f;
         float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
         double acc_a = 0.0, acc_b = 0.0;
-        float smin = __builtin_inff();
+        int smin = 0x7fffffff;
         auto vol = [&](const Pt<R> &p, float &sg, bool &isl) {
             const float zr = fmaf(noa, p.Z, -rh);
             const float q = __builtin_amdgcn_sqrtf(fmaf(zr, zr, omr2));
@@ -325,7 +335,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         };
         auto island = [&](const Pt<R> &p) {
             const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
-            return ev.al * __builtin_amdgcn_rcpf(ev.an) * p.P1 * corr * ev.zx_near(noa * p.Z);
+            return iscale * p.P1 * corr * ev.zx_near(noa * p.Z);
         };
         auto pair = [&](const Pt<R> &pa, const Pt<R> &pb) {
             float sa, sb;
@@ -336,7 +346,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
                 if (ia) sa = island(pa);
                 if (ib) sb = island(pb);
             }
-            smin = fminf(smin, fminf(sa, sb));
+            smin = min(smin, min(__float_as_int(sa), __float_as_int(sb)));
             const float ea = fmaf(-sa, pa.sw, pa.tsw), eb = fmaf(-sb, pb.sw, pb.tsw);
             acc_a = fma((double)ea, (double)ea, acc_a);
             acc_b = fma((double)eb, (double)eb, acc_b);
@@ -346,7 +356,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             bool is;
             vol(p, sg, is);
             if (is) sg = island(p);
-            smin = fminf(smin, sg);
+            smin = min(smin, __float_as_int(sg));
             const float e = fmaf(-sg, p.sw, p.tsw);
             acc_a = fma((double)e, (double)e, acc_a);
         };
@@ -386,7 +396,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             }
         }
         const double acc = acc_a + acc_b;
-        return (smin > 0.0f && acc < __builtin_inf()) ? acc : __builtin_inf();
+        return (smin > 0 && acc < __builtin_inf()) ? acc : __builtin_inf();
     }
     const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
     const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
