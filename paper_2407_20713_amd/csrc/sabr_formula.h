@@ -9,7 +9,7 @@ namespace sabr {
 // LDS point record (one per strike) and row record (one per maturity).
 template <typename R>
 struct alignas(16) Pt {
-    R Z, PZ, Q1, Q2;      // beta fixed: z factor, P1 Z, (Kf)^-(1-b)/2, (Kf)^-(1-b)
+    R Z, PZW, Q1, Q2;     // beta fixed: z factor, P1 Z sqrt(weight), (Kf)^-(1-b)/2, (Kf)^-(1-b)
     R P1, lfk, lkf, T;    // leading factor, ln(f/K), ln(Kf), maturity
     R tsw, sw;            // market value times sqrt(weight), sqrt(weight)
 };
@@ -70,7 +70,7 @@ __device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const Mat
         Pt<R> p;
         p.P1 = (R)P.P1[g];
         p.Z = (R)P.Z[g];
-        p.PZ = (R)(P.P1[g] * P.Z[g]);
+        p.PZW = (R)(P.P1[g] * P.Z[g] * P.sw[g]);
         p.Q1 = (R)P.Q1[g];
         p.Q2 = (R)P.Q2[g];
         p.lfk = (R)P.lfk[g];
@@ -304,16 +304,22 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         // (P1 Z) (nu / ln 2) corr / (x / ln 2); near the money, where that form
         // cancels, al P1 corr (z / x) from the series.  The maturity factor
         // corr = 1 + T (c1a2 Q2 + c2rna Q1 + c3n2) takes its T from the row;
-        // its coefficients carry the factor nu / ln 2.  Residuals in float,
-        // their squares summed in double (the sums that decide the Metropolis
-        // test).  A vol that is not finite and positive shows in the smallest
-        // vol or makes the sum infinite or NaN.  The smallest vol is tracked
-        // on the vols' bit patterns as signed integers: for non-negative
-        // floats that order is the float order, and every float with its sign
-        // bit set (negative, -0, negative NaN) compares below +0, so `> 0`
-        // holds exactly when each vol is a positive number, +inf or a NaN
-        // with the sign bit clear; those last two make the sum infinite or
-        // NaN.  (An integer minimum needs no NaN canonicalisation.)
+        // its coefficients carry the factor nu / ln 2.  The residual
+        // sqrt(w) (target - vol) is one fma, tsw - (P1 Z sqrt(w) corr) / xb,
+        // with P1 Z sqrt(w) staged per point; residuals in float, their
+        // squares summed in double (the sums that decide the Metropolis test).
+        // A vol that is not finite and positive makes the objective +inf.
+        // Its sign is corr's: P1 > 0, sqrt(w) > 0 and Z / x(z) > 0 (x has
+        // the sign of z = (nu / al) Z; outside the island |z| is far from 0),
+        // and in the island z / x > 0; so the check is on the smallest corr,
+        // and a non-finite vol makes the sum infinite or NaN.  The smallest
+        // corr is tracked on the bit patterns as signed integers: for
+        // non-negative floats that order is the float order, and every float
+        // with its sign bit set (negative, -0, negative NaN) compares below
+        // +0, so `> 0` holds exactly when each corr is a positive number,
+        // +inf or a NaN with the sign bit clear, and those last two make the
+        // sum infinite or NaN.  (An integer minimum needs no NaN
+        // canonicalisation.)
         const float noa = ev.noa, rh = ev.rh, lb1 = ev.lb1, lb2 = ev.lb2, omr2 = ev.omr2;
         // near the money: |z| = noa |Z| < kZIsland
         // al / nu, from one hardware reciprocal: the island bound and the
@@ -323,41 +329,39 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         const float iscale = aln * 0.693147180559945309f;
         float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
         double acc_a = 0.0, acc_b = 0.0;
-        int smin = 0x7fffffff;
-        auto vol = [&](const Pt<R> &p, float &sg, bool &isl) {
+        int cmin = 0x7fffffff;
+        auto resid = [&](const Pt<R> &p, float &e, float &corr, bool &isl) {
             const float zr = fmaf(noa, p.Z, -rh);
             const float q = __builtin_amdgcn_sqrtf(fmaf(zr, zr, omr2));
             const float L = __builtin_amdgcn_logf(q + fabsf(zr));
             const float xb = zr >= 0.0f ? L - lb1 : lb2 - L;
-            const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
-            sg = p.PZ * corr * __builtin_amdgcn_rcpf(xb);
+            corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
+            e = fmaf(-(p.PZW * corr), __builtin_amdgcn_rcpf(xb), p.tsw);
             isl = fabsf(p.Z) < zthr;
         };
-        auto island = [&](const Pt<R> &p) {
-            const float corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
-            return iscale * p.P1 * corr * ev.zx_near(noa * p.Z);
+        auto island = [&](const Pt<R> &p, float corr) {
+            const float sg = iscale * p.P1 * corr * ev.zx_near(noa * p.Z);
+            return fmaf(-sg, p.sw, p.tsw);
         };
         auto pair = [&](const Pt<R> &pa, const Pt<R> &pb) {
-            float sa, sb;
+            float ea, eb, ca, cb;
             bool ia, ib;
-            vol(pa, sa, ia);
-            vol(pb, sb, ib);
+            resid(pa, ea, ca, ia);
+            resid(pb, eb, cb, ib);
             if (__builtin_expect(ia || ib, 0)) {
-                if (ia) sa = island(pa);
-                if (ib) sb = island(pb);
+                if (ia) ea = island(pa, ca);
+                if (ib) eb = island(pb, cb);
             }
-            smin = min(smin, min(__float_as_int(sa), __float_as_int(sb)));
-            const float ea = fmaf(-sa, pa.sw, pa.tsw), eb = fmaf(-sb, pb.sw, pb.tsw);
+            cmin = min(cmin, min(__float_as_int(ca), __float_as_int(cb)));
             acc_a = fma((double)ea, (double)ea, acc_a);
             acc_b = fma((double)eb, (double)eb, acc_b);
         };
         auto single = [&](const Pt<R> &p) {
-            float sg;
+            float e, c;
             bool is;
-            vol(p, sg, is);
-            if (is) sg = island(p);
-            smin = min(smin, __float_as_int(sg));
-            const float e = fmaf(-sg, p.sw, p.tsw);
+            resid(p, e, c, is);
+            if (is) e = island(p, c);
+            cmin = min(cmin, __float_as_int(c));
             acc_a = fma((double)e, (double)e, acc_a);
         };
         for (int i = 0; i < n_mat; ++i) {
@@ -396,7 +400,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             }
         }
         const double acc = acc_a + acc_b;
-        return (smin > 0 && acc < __builtin_inf()) ? acc : __builtin_inf();
+        return (cmin > 0 && acc < __builtin_inf()) ? acc : __builtin_inf();
     }
     const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
     const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
