@@ -578,6 +578,30 @@ def test_mc_objective_calibration_recovers_truth(S, ctx):
     assert r["f"] < 1e-6
 
 
+@pytest.mark.parametrize("prec,n_chains", [(1, 64), (1, 1024), (0, 1024)])
+def test_sa_never_accepts_negative_vols(S, ctx, oracle, prec, n_chains):
+    """A state whose model vol is not positive has objective +inf (the
+    objective's reading of a non-positive vol) and is never accepted.  Ten-year
+    maturity with rho near -1 and nu near 2: the Hagan maturity factor of eq.
+    "haganf" turns the vol negative everywhere in the box (checked on a grid of
+    the box with the oracle), so every chain, in the float hot loop (one and
+    two lanes per chain) and in double, rejects every proposal."""
+    g = inputs.make_grid([10.0], [[0.7, 1.0, 1.4]], f0=1.0)
+    lb, ub = np.array([0.2, -0.99, 1.9]), np.array([0.21, -0.98, 2.0])
+    for a in np.linspace(lb[0], ub[0], 4):
+        for r in np.linspace(lb[1], ub[1], 4):
+            for n in np.linspace(lb[2], ub[2], 4):
+                assert max(oracle.sigma_hagan(K, 1.0, 10.0, a, 0.5, r, n) for K in g.K) < 0.0
+    tgt = np.full(3, 0.3)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.5, lb, ub),
+                    precision=prec, n_chains=n_chains, n_iters=40, chain_len=10, seed=0x5EED)
+    got = S.sabr_calibrate(ctx, [req])[0]
+    say("negative vols", prec, n_chains, got["n_accept"], got["f"])
+    assert got["n_accept"] == 0
+    assert not np.isfinite(got["f"])
+    np.testing.assert_array_equal(got["x"][:3], (lb + ub) / 2)
+
+
 @pytest.mark.parametrize("n_chains,n_iters,chain_len,n_strikes", [
     (1, 1, 10, 15),      # one chain, one iteration
     (3, 7, 10, 15),      # a single, partial temperature level
