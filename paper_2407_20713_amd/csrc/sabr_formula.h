@@ -352,7 +352,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
                 if (ia) ea = island(pa, ca);
                 if (ib) eb = island(pb, cb);
             }
-            cmin = min(cmin, min(__float_as_int(ca), __float_as_int(cb)));
+            cmin = min(min(cmin, __float_as_int(ca)), __float_as_int(cb));
             acc_a = fma((double)ea, (double)ea, acc_a);
             acc_b = fma((double)eb, (double)eb, acc_b);
         };
