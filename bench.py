@@ -49,7 +49,7 @@ SLOTS_PER_PT_EVAL = 39
 # the 262144 read, WRITE_SIZE exactly 262144): profiles/counters_sa_kernel_static_surface.md.
 # Almost all of it is the level-end exchange between workgroups (candidate
 # slots written and watched across the chip's L2 caches); the grids are read once.
-SA_FETCH_KIB, SA_WRITE_KIB = 1166202.4583, 144097.3125
+SA_FETCH_KIB, SA_WRITE_KIB = 1165956.0833, 144097.3125
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.1587, 1.0
 SA_TRAFFIC_BYTES = (SA_FETCH_KIB * FETCH_SCALE + SA_WRITE_KIB * WRITE_SCALE) * 1024
 # False once sa_kernel has changed since the counters above were taken (traffic then null)

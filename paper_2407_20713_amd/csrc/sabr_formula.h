@@ -9,7 +9,7 @@ namespace sabr {
 // LDS point record (one per strike) and row record (one per maturity).
 template <typename R>
 struct alignas(16) Pt {
-    R Z, PZW, Q1, Q2;     // beta fixed: z factor, P1 Z sqrt(weight), (Kf)^-(1-b)/2, (Kf)^-(1-b)
+    R Z, PZW, Q1, Q2;     // beta fixed: z factor, |P1 Z| sqrt(weight), (Kf)^-(1-b)/2, (Kf)^-(1-b)
     R P1, lfk, lkf, T;    // leading factor, ln(f/K), ln(Kf), maturity
     R tsw, sw;            // market value times sqrt(weight), sqrt(weight)
 };
@@ -70,7 +70,7 @@ __device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const Mat
         Pt<R> p;
         p.P1 = (R)P.P1[g];
         p.Z = (R)P.Z[g];
-        p.PZW = (R)(P.P1[g] * P.Z[g] * P.sw[g]);
+        p.PZW = (R)fabs(P.P1[g] * P.Z[g] * P.sw[g]);
         p.Q1 = (R)P.Q1[g];
         p.Q2 = (R)P.Q2[g];
         p.lfk = (R)P.lfk[g];
@@ -304,10 +304,14 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         // (P1 Z) (nu / ln 2) corr / (x / ln 2); near the money, where that form
         // cancels, al P1 corr (z / x) from the series.  The maturity factor
         // corr = 1 + T (c1a2 Q2 + c2rna Q1 + c3n2) takes its T from the row;
-        // its coefficients carry the factor nu / ln 2.  The residual
-        // sqrt(w) (target - vol) is one fma, tsw - (P1 Z sqrt(w) corr) / xb,
-        // with P1 Z sqrt(w) staged per point; residuals in float, their
-        // squares summed in double (the sums that decide the Metropolis test).
+        // its coefficients carry the factor nu / ln 2.  Both branches of x / ln 2
+        // are +-(L - lb) with lb = log2(1 - rho) or log2(1 + rho), and x has
+        // the sign of z, that is of Z, as P1 Z does; so (P1 Z) / x =
+        // |P1 Z| / |L - lb| and the sign never has to be applied.  The
+        // residual sqrt(w) (target - vol) is one fma,
+        // tsw - (|P1 Z| sqrt(w) corr) / |L - lb|, with |P1 Z| sqrt(w) staged
+        // per point; residuals in float, their squares summed in double (the
+        // sums that decide the Metropolis test).
         // A vol that is not finite and positive makes the objective +inf.
         // Its sign is corr's: P1 > 0, sqrt(w) > 0 and Z / x(z) > 0 (x has
         // the sign of z = (nu / al) Z; outside the island |z| is far from 0),
@@ -334,9 +338,9 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             const float zr = fmaf(noa, p.Z, -rh);
             const float q = __builtin_amdgcn_sqrtf(fmaf(zr, zr, omr2));
             const float L = __builtin_amdgcn_logf(q + fabsf(zr));
-            const float xb = zr >= 0.0f ? L - lb1 : lb2 - L;
+            const float d = L - (zr >= 0.0f ? lb1 : lb2);
             corr = fmaf(k1, p.Q2, fmaf(k2, p.Q1, k0));
-            e = fmaf(-(p.PZW * corr), __builtin_amdgcn_rcpf(xb), p.tsw);
+            e = fmaf(-(p.PZW * corr), __builtin_amdgcn_rcpf(fabsf(d)), p.tsw);
             isl = fabsf(p.Z) < zthr;
         };
         auto island = [&](const Pt<R> &p, float corr) {
