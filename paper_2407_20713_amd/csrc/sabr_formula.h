@@ -313,10 +313,10 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         // per point; residuals in float, their squares summed in double (the
         // sums that decide the Metropolis test).
         // A vol that is not finite and positive makes the objective +inf.
-        // Its sign is corr's: P1 > 0, sqrt(w) > 0 and Z / x(z) > 0 (x has
-        // the sign of z = (nu / al) Z; outside the island |z| is far from 0),
-        // and in the island z / x > 0; so the check is on the smallest corr,
-        // and a non-finite vol makes the sum infinite or NaN.  The smallest
+        // Its sign is corr's: the other factors are |P1 Z| sqrt(w) and
+        // 1 / |L - lb| (in the island P1, sqrt(w) and z / x, all positive),
+        // so the check is on the smallest corr, and a non-finite vol makes
+        // the sum infinite or NaN.  The smallest
         // corr is tracked on the bit patterns as signed integers: for
         // non-negative floats that order is the float order, and every float
         // with its sign bit set (negative, -0, negative NaN) compares below
