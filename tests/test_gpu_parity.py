@@ -578,6 +578,38 @@ def test_mc_objective_calibration_recovers_truth(S, ctx):
     assert r["f"] < 1e-6
 
 
+@pytest.mark.parametrize("n_chains", [64, 1024])
+@pytest.mark.parametrize("formula", [0, 1])
+@pytest.mark.parametrize("weighting", [0, 1])
+def test_sa_float_objective_at_result_matches_oracle(S, ctx, oracle, n_chains, formula, weighting):
+    """The annealing kernel's own float objective (one and two lanes per
+    chain; ragged rows of 7, 7 and 30 strikes, strikes at and next to the
+    forward) at the state it returns, without polish, against the oracle's
+    FP64 objective at those parameters, within what a vol error of
+    delta = 2e-5 allows (as for the objective batch)."""
+    K0 = np.exp(np.linspace(-0.4, 0.5, 7))
+    K1 = 1.3 * np.exp(np.array([-1e-2, -1e-4, -1e-7, 0.0, 1e-7, 1e-4, 1e-2]))
+    K2 = np.exp(np.linspace(-0.7, 0.6, 30))
+    g = inputs.make_grid([0.1, 1.3, 6.0], [K0, K1, K2], f0=1.3)
+    m = omkt(oracle, g)
+    tgt = oracle.model_vols(m, oracle.STATIC, [0.25, -0.4, 0.7], 0.6, False, formula) + 2e-3
+    m.target = tgt
+    lb, ub = inputs.box(inputs.STATIC)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.6, lb, ub),
+                    formula=formula, weighting=weighting, precision=S.SABR_FP32, n_chains=n_chains,
+                    n_iters=300, chain_len=10, cooling=0.99 ** (1000.0 / 300), seed=0xF10A7 + formula)
+    got = S.sabr_calibrate(ctx, [req])[0]
+    x = np.asarray(got["x"][:3])
+    ref_f = oracle.objective_formula(m, oracle.STATIC, x, 0.6, False, formula, weighting)
+    ref_v = oracle.model_vols(m, oracle.STATIC, x, 0.6, False, formula)
+    w = np.ones_like(tgt) if weighting == 0 else 1.0 / tgt ** 2
+    delta = 2e-5
+    tol = np.sum((2 * np.abs(tgt - ref_v) * delta + delta ** 2) * w) + 1e-6 * ref_f
+    say("float objective at result", n_chains, formula, weighting, got["f"], ref_f, tol)
+    assert got["status"] == 0 and np.isfinite(ref_f)
+    assert abs(got["f"] - ref_f) <= tol
+
+
 @pytest.mark.parametrize("prec,n_chains", [(1, 64), (1, 1024), (0, 1024)])
 def test_sa_never_accepts_negative_vols(S, ctx, oracle, prec, n_chains):
     """A state whose model vol is not positive has objective +inf (the
