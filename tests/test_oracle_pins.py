@@ -13,6 +13,7 @@ import os
 import numpy as np
 import pytest
 import scipy.integrate as si
+import scipy.optimize as so
 import scipy.special as sp
 import scipy.stats as st
 
@@ -108,6 +109,38 @@ def test_hagan_symmetric_smile_rho0_beta1(oracle, l):
     c = oracle.sigma_hagan(f * math.exp(l), f, 2.0, 0.3, 1.0, -0.5, 0.8)
     d = oracle.sigma_hagan(f * math.exp(-l), f, 2.0, 0.3, 1.0, -0.5, 0.8)
     assert c < d
+
+
+def test_hagan_normal_limit_is_bachelier(oracle):
+    """beta = 0, nu -> 0: the model is F_T = f + alpha W_T (Bachelier), whose
+    call price has a closed form.  Eq. "haganf" is the small-T expansion of
+    the Black vol implied by that price: it matches the implied vol (scipy
+    root of Black's formula) to 1e-6 for T <= 0.4 at strikes 0.8..1.25, and
+    at the money its error shrinks like T^2 (the first neglected order).  A
+    dropped or mis-signed (1-beta)^2 l^2 / 24 term or T correction misses by
+    1e-4 or more."""
+    def bachelier(f, K, T, a):
+        sd = a * math.sqrt(T)
+        d = (f - K) / sd
+        return (f - K) * st.norm.cdf(d) + sd * st.norm.pdf(d)
+
+    def black(f, K, T, sig):
+        sd = sig * math.sqrt(T)
+        d1 = (math.log(f / K) + 0.5 * sd * sd) / sd
+        return f * st.norm.cdf(d1) - K * st.norm.cdf(d1 - sd)
+
+    def implied(f, K, T, price):
+        return so.brentq(lambda v: black(f, K, T, v) - price, 1e-6, 5.0, xtol=1e-15, rtol=1e-15)
+
+    f, a = 1.0, 0.2
+    atm = {}
+    for T in (0.1, 0.2, 0.4):
+        for K in (0.8, 0.9, 1.0, 1.1, 1.25):
+            err = oracle.sigma_hagan(K, f, T, a, 0.0, 0.0, 1e-9) - implied(f, K, T, bachelier(f, K, T, a))
+            assert abs(err) < 1e-6, (T, K, err)
+            if K == 1.0:
+                atm[T] = err
+    assert 3.0 < atm[0.2] / atm[0.1] < 5.0 and 3.0 < atm[0.4] / atm[0.2] < 5.0, atm
 
 
 @pytest.mark.parametrize("beta", [0.0, 0.3, 0.7, 1.0])
