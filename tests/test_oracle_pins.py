@@ -143,6 +143,36 @@ def test_hagan_normal_limit_is_bachelier(oracle):
     assert 3.0 < atm[0.2] / atm[0.1] < 5.0 and 3.0 < atm[0.4] / atm[0.2] < 5.0, atm
 
 
+def test_obloj_normal_limit_carries_the_printed_denominator(oracle):
+    """Eq. "sigma-SABR" as printed keeps Hagan's 1 / (1 + (1-beta)^2 l^2 / 24
+    + (1-beta)^4 l^4 / 1920) beside Oblój's leading term (the reading taken:
+    implement as printed).  In the normal limit (beta = 0, nu -> 0), where
+    Oblój's leading term alone is already the Bachelier-implied vol to first
+    order in T, the printed form therefore sits below the Bachelier-implied
+    vol by exactly that factor off the money (4.6e-4 at K = 0.8, independent
+    of T), and times the factor it matches to 1e-6, like eq. "haganf"."""
+    def bachelier(f, K, T, a):
+        sd = a * math.sqrt(T)
+        d = (f - K) / sd
+        return (f - K) * st.norm.cdf(d) + sd * st.norm.pdf(d)
+
+    def black(f, K, T, sig):
+        sd = sig * math.sqrt(T)
+        d1 = (math.log(f / K) + 0.5 * sd * sd) / sd
+        return f * st.norm.cdf(d1) - K * st.norm.cdf(d1 - sd)
+
+    f, a = 1.0, 0.2
+    for T in (0.1, 0.4):
+        for K in (0.8, 0.9, 1.1, 1.25):
+            iv = so.brentq(lambda v: black(f, K, T, v) - bachelier(f, K, T, a), 1e-6, 5.0,
+                           xtol=1e-15, rtol=1e-15)
+            ob = oracle.sigma_obloj(K, f, T, a, 0.0, 0.0, 1e-9)
+            l = math.log(f / K)
+            den = 1.0 + l * l / 24.0 + l ** 4 / 1920.0
+            assert abs(ob * den - iv) < 1e-6, (T, K)
+            assert ob < iv - 5e-5
+
+
 @pytest.mark.parametrize("beta", [0.0, 0.3, 0.7, 1.0])
 @pytest.mark.parametrize("rho", [-0.8, 0.0, 0.6])
 def test_atm_forms_agree(oracle, beta, rho):
