@@ -553,14 +553,16 @@ double or_objective_mc(int model, int weighting, double beta, int beta_free, int
 /* Case II constraints (Section 5, Technique II): rho(t) in [-1, 1] and      */
 /* nu(t) > 0 for every 0 < t <= T_max.  Each function is (c0 + c1 t) e^(-k t) */
 /* + d; its extrema on [0, T_max] lie at the ends or at the one stationary   */
-/* point t* = 1/k - c0/c1 (k > 0, c1 != 0).  The value at t = 0 stands for   */
+/* point t* = 1/k - c0/c1 (k != 0, c1 != 0; the derivative e^(-k t) (c1 -     */
+/* k (c0 + c1 t)) vanishes there whatever the sign of k, so growing as well  */
+/* as decaying exponentials are covered).  The value at t = 0 stands for     */
 /* the limit t -> 0+.                                                         */
 /* ------------------------------------------------------------------------ */
 static void fn_extrema(double c0, double c1, double k, double d, double tmax, double *lo, double *hi)
 {
     double v0 = c0 + d, v1 = (c0 + c1 * tmax) * exp(-k * tmax) + d;
     *lo = fmin(v0, v1); *hi = fmax(v0, v1);
-    if (k > 0.0 && c1 != 0.0) {
+    if (k != 0.0 && c1 != 0.0) {
         double ts = 1.0 / k - c0 / c1;
         if (ts > 0.0 && ts < tmax) {
             double v = (c0 + c1 * ts) * exp(-k * ts) + d;

@@ -552,6 +552,72 @@ def test_case2_feasibility_matches_dense_sampling(oracle):
     assert n_agree > 250 and 10 < n_feasible < n_agree - 10
 
 
+@pytest.mark.parametrize("x,t_max,feasible", [
+    # rho(t) = (-0.9 + 0.3 t) e^(0.5 t) - 0.05: both ends inside [-1, 1], interior minimum -1.039 at t = 1
+    ([0.2, -0.9, 0.6, -0.5, 0.3, -0.05, 0.0, 0.3, 0.0], 2.0, False),
+    # the same with d_rho = +0.05: minimum -0.939, feasible
+    ([0.2, -0.9, 0.6, -0.5, 0.3, 0.05, 0.0, 0.3, 0.0], 2.0, True),
+    # rho(t) = (0.9 - 0.3 t) e^(0.5 t) + 0.05: interior maximum 1.039 at t = 1
+    ([0.2, 0.9, 0.6, -0.5, 0.3, 0.05, 0.0, -0.3, 0.0], 2.0, False),
+    # nu(t) = (-0.6 + 0.2 t) e^(0.4 t) + 0.605: ends 0.005 and 0.333, interior minimum -0.0057 at t = 0.5
+    ([0.2, 0.0, -0.6, 0.0, -0.4, 0.0, 0.605, 0.0, 0.2], 2.5, False),
+])
+def test_case2_feasibility_growing_exponentials(oracle, x, t_max, feasible):
+    """Case II functions with negative rates (growing exponentials) have their
+    interior extremum at t* = 1/k - c0/c1 as well; dense sampling decides
+    each case and the analytic check must agree."""
+    x = np.array(x)
+    t = np.linspace(1e-9, t_max, 400001)
+    rho = (x[1] + x[7] * t) * np.exp(-x[3] * t) + x[5]
+    nu = (x[2] + x[8] * t) * np.exp(-x[4] * t) + x[6]
+    margin = min(1 - rho.max(), rho.min() + 1, nu.min())
+    assert abs(margin) > 1e-3 and (margin > 0) == feasible
+    assert oracle.case2_feasible(x, t_max) == feasible
+
+
+# --- objective weighting (Section 3) ---------------------------------------------------
+@pytest.mark.parametrize("model", [inputs.STATIC, inputs.DYN_I, inputs.DYN_II])
+def test_relative_objective_closed_form(oracle, model):
+    """Targets D_j = m_j (1 + e_j) around the model values m_j give, under the
+    paper's relative squared errors, f = sum (e_j / (1 + e_j))^2 exactly, and
+    under absolute errors f = sum (e_j m_j)^2.  A relative error taken
+    against the model instead of the market (sum e_j^2), or a mixed-up
+    point index, fails both."""
+    g = inputs.make_grid([0.5, 2.0], [np.exp(np.linspace(-0.3, 0.3, 5)), np.exp(np.linspace(-0.5, 0.5, 7))])
+    m = oracle.Market(g.T, g.fwd, g.offs, g.K)
+    x = {inputs.STATIC: [0.25, -0.3, 0.6], inputs.DYN_I: [0.25, -0.3, 0.6, 0.4, 0.7],
+         inputs.DYN_II: [0.25, -0.3, 0.6, 0.4, 0.7, 0.05, 0.02, 0.1, 0.2]}[model]
+    mv = oracle.model_vols(m, model, x, 0.7)
+    e = np.linspace(-0.2, 0.3, len(mv)) * np.where(np.arange(len(mv)) % 2, 1.0, -0.5)
+    m.target = mv * (1.0 + e)
+    rel = oracle.objective_formula(m, model, x, 0.7, weighting=oracle.RELATIVE)
+    ab = oracle.objective_formula(m, model, x, 0.7, weighting=oracle.ABSOLUTE)
+    assert rel == pytest.approx(np.sum((e / (1.0 + e)) ** 2), rel=1e-13)
+    assert ab == pytest.approx(np.sum((e * mv) ** 2), rel=1e-12)
+    assert abs(rel - np.sum(e ** 2)) > 1e-3 * rel
+
+
+@pytest.mark.parametrize("model,x", [(inputs.STATIC, [0.25, -0.3, 0.6]), (inputs.DYN_I, [0.25, -0.3, 0.6, 0.4, 0.7]),
+                                     (inputs.DYN_II, [0.25, -0.3, 0.6, 0.4, 0.7, 0.05, 0.02, 0.1, 0.2])])
+def test_mc_objective_closed_forms(oracle, model, x):
+    """The Monte Carlo objective on common paths: targets priced on the same
+    seed and paths give f = 0 exactly; targets P_j (1 + e_j) give
+    f = sum (e_j / (1 + e_j))^2 (relative) and sum (e_j P_j)^2 (absolute);
+    another path seed gives f > 0."""
+    g = inputs.make_grid([0.25, 0.5], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0, disc=[0.99, 0.98])
+    m = oracle.Market(g.T, g.fwd, g.offs, g.K, disc=g.disc)
+    p, _ = oracle.mc_prices(m, model, x, 0.7, 256, 250, 21)
+    m.target = p
+    assert oracle.objective_mc(m, model, x, 0.7, 256, 250, 21, weighting=oracle.RELATIVE) == 0.0
+    assert oracle.objective_mc(m, model, x, 0.7, 256, 250, 22, weighting=oracle.RELATIVE) > 1e-8
+    e = np.array([0.1, -0.05, 0.2, -0.15, 0.05, 0.3])
+    m.target = p * (1.0 + e)
+    rel = oracle.objective_mc(m, model, x, 0.7, 256, 250, 21, weighting=oracle.RELATIVE)
+    ab = oracle.objective_mc(m, model, x, 0.7, 256, 250, 21, weighting=oracle.ABSOLUTE)
+    assert rel == pytest.approx(np.sum((e / (1.0 + e)) ** 2), rel=1e-12)
+    assert ab == pytest.approx(np.sum((e * p) ** 2), rel=1e-12)
+
+
 # --- simulated annealing (Section 5, Technique I) ----------------------------------
 def _smile_market(oracle, x_true, noise_sd=0.0, seed=1):
     g = inputs.single_smile()
