@@ -84,6 +84,9 @@ def lib():
                                       _D, _D, _D, _I32, _D, _D, C.c_int64, C.c_int32, C.c_uint64]
         L.or_objective_mc.restype = C.c_double
         L.or_case2_feasible.argtypes = [_D, C.c_double]
+        L.or_mc_cliquet.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _D, C.c_double, C.c_double, C.c_int,
+                                    _D, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int32,
+                                    C.c_uint64, _D, _D]
         L.or_calibrate.argtypes = [C.POINTER(SAProblem), C.POINTER(SAResult)]
         L.or_calibrate_levels.argtypes = [C.POINTER(SAProblem), C.c_int32, C.c_int32, _D, _D, _D,
                                           _D, _I64, _I64]
@@ -225,6 +228,20 @@ def objective_mc(market, model, x, beta, n_paths, steps_per_year, seed, beta_fre
                                  market.n_mat, _dp(market.T), _dp(market.fwd), _dp(market.disc),
                                  market.offs.ctypes.data_as(_I32), _dp(market.K),
                                  _dp(market.target), int(n_paths), int(steps_per_year), int(seed))
+
+
+def mc_cliquet(model, x, beta, f0, reset_T, local_floor, local_cap, global_floor, global_cap, n_paths,
+               steps_per_year, seed, disc=1.0, beta_free=False):
+    """Cliquet price and standard error on the paths of mc_prices."""
+    x = _f64(x)
+    rt = _f64(reset_T)
+    price, se = C.c_double(), C.c_double()
+    rc = lib().or_mc_cliquet(model, beta, int(beta_free), len(x), _dp(x), f0, disc, len(rt), _dp(rt),
+                             local_floor, local_cap, global_floor, global_cap, int(n_paths), int(steps_per_year),
+                             int(seed), C.byref(price), C.byref(se))
+    if rc:
+        raise ValueError("or_mc_cliquet failed")
+    return price.value, se.value
 
 
 class _Keep:

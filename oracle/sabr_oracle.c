@@ -527,6 +527,78 @@ int or_mc_prices(int model, double beta, int beta_free, int n_par, const double 
     return 0;
 }
 
+/* Cliquet option (Section 6, pricing with calibrated parameters, eqs.      */
+/* "eq_cliquet" and "eq:cliquet_global"): along each path of the scheme of  */
+/* eq. "dis_SABRd" (printed multiplicative form, the same normals as        */
+/* or_mc_prices) the forward is read at the reset dates d_1 < ... < d_D      */
+/* (step max(1, floor(d_i / dt)), as for the European maturities; S_T = F_T, */
+/* Section 4), the returns R_i = (F_{d_i} - F_{d_{i-1}}) / F_{d_{i-1}},      */
+/* i = 2..D, are clamped to [F_l, C_l] and summed, and the sum is clamped to */
+/* [F_g, C_g].  Readings: the printed global payoff max(C_g, min(F_g, .))    */
+/* would be the constant C_g whenever F_g < C_g, so the floor and cap are    */
+/* read the other way round, max(F_g, min(C_g, .)); a return from an        */
+/* absorbed (zero) forward is -1.  price = disc * mean(payoff) (Neumaier     */
+/* sums), std_err = disc * sd / sqrt(N).                                    */
+int or_mc_cliquet(int model, double beta, int beta_free, int n_par, const double *x, double f0, double disc,
+                  int n_reset, const double *reset_T, double local_floor, double local_cap,
+                  double global_floor, double global_cap, int64_t n_paths, int32_t steps_per_year,
+                  uint64_t seed, double *price, double *std_err)
+{
+    or_params p;
+    if (unpack(model, beta, beta_free, n_par, x, &p)) return -1;
+    if (n_paths < 1 || steps_per_year < 1 || n_reset < 2 || !(f0 > 0.0)) return -1;
+    fn_params q = { p.rho0, p.nu0, p.a, p.b, p.drho, p.dnu, p.qrho, p.qnu, model };
+    int32_t *ms = malloc(sizeof(int32_t) * (size_t)n_reset);
+    if (!ms) return -2;
+    for (int i = 0; i < n_reset; ++i) {
+        ms[i] = n_steps(reset_T[i], steps_per_year);
+        if (i > 0 && ms[i] <= ms[i - 1]) { free(ms); return -1; }   /* dates on distinct steps, increasing */
+    }
+    int32_t m_max = ms[n_reset - 1];
+    double dt = 1.0 / (double)steps_per_year;
+    double sdt = sqrt(dt);
+    nsum s1 = { 0.0, 0.0 }, s2 = { 0.0, 0.0 };
+    for (int64_t path = 0; path < n_paths; ++path) {
+        double al = p.alpha, F = f0;
+        int absorbed = 0, next = 0;
+        double F_prev = 0.0, sum = 0.0;
+        for (int32_t i = 0; i < m_max; ++i) {
+            if (!absorbed) {
+                double z1, z2;
+                or_mc_normals(seed, path, i, &z1, &z2);
+                double t = i * dt;
+                double nu = (model == OR_STATIC) ? p.nu0 : fn_nu(&q, t);
+                double rho = (model == OR_STATIC) ? p.rho0 : fn_rho(&q, t);
+                double nuhat = al * pow(F, p.beta - 1.0);
+                double al_next = al * exp(nu * z1 * sdt - nu * nu * dt / 2.0);
+                double F_next = F * exp(nuhat * (rho * z1 + z2 * sqrt(1.0 - rho * rho)) * sdt
+                                        - nuhat * nuhat * dt / 2.0);
+                al = al_next;
+                F = F_next;
+                if (!(F >= OR_EPS_ABS * f0)) { F = 0.0; absorbed = 1; }
+            }
+            if (next < n_reset && ms[next] == i + 1) {
+                if (next > 0) {
+                    double R = (F_prev > 0.0) ? (F - F_prev) / F_prev : -1.0;
+                    sum += fmax(fmin(R, local_cap), local_floor);
+                }
+                F_prev = F;
+                ++next;
+            }
+        }
+        double v = fmax(global_floor, fmin(global_cap, sum));
+        nsum_add(&s1, v);
+        nsum_add(&s2, v * v);
+    }
+    double mean = (s1.s + s1.c) / (double)n_paths;
+    double ex2 = (s2.s + s2.c) / (double)n_paths;
+    double var = (n_paths > 1) ? fmax(ex2 - mean * mean, 0.0) * (double)n_paths / (double)(n_paths - 1) : 0.0;
+    *price = disc * mean;
+    if (std_err) *std_err = disc * sqrt(var / (double)n_paths);
+    free(ms);
+    return 0;
+}
+
 /* Objective of Technique II: relative (or absolute) squared price errors   */
 /* with Monte Carlo model prices on fixed paths (common random numbers).    */
 double or_objective_mc(int model, int weighting, double beta, int beta_free, int n_par,

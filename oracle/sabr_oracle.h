@@ -68,6 +68,15 @@ int or_mc_prices(int model, double beta, int beta_free, int n_par, const double 
                  const int32_t *offs, const double *K, int64_t n_paths, int32_t steps_per_year,
                  uint64_t seed, double *price, double *std_err);
 
+/* cliquet option with local and global limits (Section 6) on the paths of */
+/* or_mc_prices: reset dates reset_T[n_reset] (increasing), returns         */
+/* i = 2..n_reset clamped to [local_floor, local_cap], their sum clamped to */
+/* [global_floor, global_cap] */
+int or_mc_cliquet(int model, double beta, int beta_free, int n_par, const double *x, double f0, double disc,
+                  int n_reset, const double *reset_T, double local_floor, double local_cap,
+                  double global_floor, double global_cap, int64_t n_paths, int32_t steps_per_year,
+                  uint64_t seed, double *price, double *std_err);
+
 /* objective of the Monte Carlo technique */
 double or_objective_mc(int model, int weighting, double beta, int beta_free, int n_par,
                        const double *x, int n_mat, const double *T, const double *fwd,

@@ -527,6 +527,61 @@ def test_printed_mc_prices(oracle):
         assert abs(p[0] - printed) < 3.0 * math.sqrt(2.0) * se[0]
 
 
+# --- cliquet option (Section 6) ------------------------------------------------------
+RESETS = [0.25, 0.5, 0.75, 1.0]          # the paper's T = 12 months, D = 4, d_i = i T / D
+
+
+def _black_unit(K, var):
+    """E[(X - K)^+] for lognormal X with E[X] = 1 and Var[ln X] = var (scipy)."""
+    from scipy.stats import norm
+    sd = math.sqrt(var)
+    d1 = (-math.log(K) + 0.5 * var) / sd
+    return norm.cdf(d1) - K * norm.cdf(d1 - sd)
+
+
+def test_cliquet_lognormal_closed_form(oracle):
+    """beta = 1, nu = 0: the scheme is exact geometric Brownian motion, the
+    returns are independent and lognormal, and clamp(R, Fl, Cl) =
+    Fl + (R - Fl)^+ - (R - Cl)^+, so with the global limits out of reach the
+    price is sum_i [Fl + C(1 + Fl) - C(1 + Cl)] with Black's C on a unit
+    forward over each reset period (63, 62, 63 steps of 1/250)."""
+    sig, Fl, Cl, D = 0.25, -0.02, 0.02, 0.97
+    p, se = oracle.mc_cliquet(oracle.STATIC, [sig, 0.3, 0.0], 1.0, 1.3, RESETS, Fl, Cl, -1e9, 1e9, 1 << 15, 250, 19,
+                              disc=D)
+    steps = [62, 125, 187, 250]
+    ref = 0.0
+    for i in range(1, 4):
+        var = sig * sig * (steps[i] - steps[i - 1]) / 250.0
+        ref += Fl + _black_unit(1.0 + Fl, var) - _black_unit(1.0 + Cl, var)
+    assert abs(p - D * ref) < 3.5 * se, (p, D * ref, se)
+
+
+def test_cliquet_martingale_returns(oracle):
+    """Without limits the payoff is the sum of the returns, and every step of
+    the log-Euler scheme is a mean-one multiplicative increment given the
+    past, so the price is 0 within the error, for dynamic SABR too."""
+    x = [0.3, -0.4, 0.8, 0.5, 0.7]
+    p, se = oracle.mc_cliquet(oracle.DYN_I, x, 0.8, 1.0, RESETS, -1e9, 1e9, -1e9, 1e9, 1 << 14, 250, 23)
+    assert abs(p) < 3.5 * se and se > 0
+
+
+def test_cliquet_limits_are_exact(oracle):
+    """Equal global floor and cap fix the payoff (price = disc c, no error);
+    equal local limits c make the sum 3 c, then clamped globally; any price
+    lies within the payoff's bounds."""
+    x = [0.3, -0.4, 0.8]
+    p, se = oracle.mc_cliquet(oracle.STATIC, x, 0.7, 1.0, RESETS, -0.02, 0.02, 0.05, 0.05, 512, 250, 3, disc=0.9)
+    assert p == pytest.approx(0.9 * 0.05, rel=1e-15) and se < 1e-15
+    p, se = oracle.mc_cliquet(oracle.STATIC, x, 0.7, 1.0, RESETS, 0.01, 0.01, -1.0, 1.0, 512, 250, 3)
+    assert p == pytest.approx(0.03, rel=1e-14) and se < 1e-15
+    p, se = oracle.mc_cliquet(oracle.STATIC, x, 0.7, 1.0, RESETS, 0.04, 0.04, 0.0, 0.1, 512, 250, 3)
+    assert p == pytest.approx(0.1, rel=1e-15)
+    # the paper's limits: local [-0.02, 0.02], global [0, 0.2]: price in [0, 0.06]
+    p, se = oracle.mc_cliquet(oracle.DYN_I, [0.3, -0.4, 0.8, 0.5, 0.7], 1.0, 1.0, RESETS, -0.02, 0.02, 0.0, 0.2,
+                              4096, 250, 5)
+    assert 0.0 < p < 0.06
+
+
 # --- case II constraint (Section 5, Technique II) -------------------------------------
 def test_case2_feasibility_matches_dense_sampling(oracle):
     """The analytic extremum check agrees with dense sampling of rho(t), nu(t)
