@@ -87,6 +87,11 @@ def lib():
         L.or_mc_cliquet.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _D, C.c_double, C.c_double, C.c_int,
                                     _D, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int32,
                                     C.c_uint64, _D, _D]
+        L.or_atm_vol.argtypes = [C.c_int, _D, _D, C.c_double]
+        L.or_atm_vol.restype = C.c_double
+        L.or_beta_from_atm.argtypes = [C.c_int, _D, _D, _D, _D]
+        L.or_atm_seed.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _D, _D, C.c_int, _D, _D, _I32, _D, _D,
+                                  _D]
         L.or_calibrate.argtypes = [C.POINTER(SAProblem), C.POINTER(SAResult)]
         L.or_calibrate_levels.argtypes = [C.POINTER(SAProblem), C.c_int32, C.c_int32, _D, _D, _D,
                                           _D, _I64, _I64]
@@ -242,6 +247,31 @@ def mc_cliquet(model, x, beta, f0, reset_T, local_floor, local_cap, global_floor
     if rc:
         raise ValueError("or_mc_cliquet failed")
     return price.value, se.value
+
+
+def atm_vol(K, vol, f):
+    K, vol = _f64(K), _f64(vol)
+    return lib().or_atm_vol(len(K), _dp(K), _dp(vol), f)
+
+
+def beta_from_atm(fwd, sigma_atm):
+    fwd, sa = _f64(fwd), _f64(sigma_atm)
+    b, a = C.c_double(), C.c_double()
+    if lib().or_beta_from_atm(len(fwd), _dp(fwd), _dp(sa), C.byref(b), C.byref(a)):
+        raise ValueError("or_beta_from_atm failed")
+    return b.value, a.value
+
+
+def atm_seed(market, model, lb, ub, beta, beta_free=False):
+    """Start point from the at-the-money vols of market.target."""
+    lb, ub = _f64(lb), _f64(ub)
+    x0 = np.zeros(len(lb))
+    rc = lib().or_atm_seed(model, beta, int(beta_free), len(lb), _dp(lb), _dp(ub), market.n_mat, _dp(market.T),
+                           _dp(market.fwd), market.offs.ctypes.data_as(_I32), _dp(market.K), _dp(market.target),
+                           _dp(x0))
+    if rc:
+        raise ValueError("or_atm_seed failed")
+    return x0
 
 
 class _Keep:

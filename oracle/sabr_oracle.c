@@ -622,6 +622,79 @@ double or_objective_mc(int model, int weighting, double beta, int beta_free, int
 }
 
 /* ------------------------------------------------------------------------ */
+/* Start point from the at-the-money vols (Section 3, after eq. "sigma-SABR"):*/
+/* sigma_ATM = sigma_model(f, f, T) gives ln sigma_ATM = ln alpha            */
+/* - (1 - beta) ln f, so beta is the slope + 1 of a log-log least-squares    */
+/* fit of sigma_ATM against f, and, with B T neglected,                      */
+/* alpha = f^(1 - beta) sigma_ATM.                                           */
+/* Readings: sigma_ATM of maturity i is the market vol at K = f_i, linear in */
+/* ln K between the two strikes around f_i (the nearest strike's vol beyond  */
+/* the row's ends); beta is estimated only when it is calibrated and the     */
+/* grid has at least two distinct forwards (otherwise the fixed beta, or the */
+/* centre of its box); alpha comes from the shortest maturity, where the     */
+/* neglected B T is smallest; alpha and beta are clamped to their box; every */
+/* other coordinate is the box centre.                                       */
+/* ------------------------------------------------------------------------ */
+double or_atm_vol(int m, const double *K, const double *vol, double f)
+{
+    /* strikes of a row are increasing */
+    if (f <= K[0]) return vol[0];
+    if (f >= K[m - 1]) return vol[m - 1];
+    int j = 0;
+    while (K[j + 1] < f) ++j;
+    double u = (log(f) - log(K[j])) / (log(K[j + 1]) - log(K[j]));
+    return vol[j] + u * (vol[j + 1] - vol[j]);
+}
+
+int or_beta_from_atm(int n, const double *fwd, const double *sigma_atm, double *beta, double *alpha)
+{
+    /* least squares of ln sigma = c0 + c1 ln f: beta = 1 + c1, alpha = e^c0 */
+    if (n < 2) return -1;
+    double mx = 0.0, my = 0.0;
+    for (int i = 0; i < n; ++i) { mx += log(fwd[i]); my += log(sigma_atm[i]); }
+    mx /= n; my /= n;
+    double sxx = 0.0, sxy = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double dx = log(fwd[i]) - mx;
+        sxx += dx * dx;
+        sxy += dx * (log(sigma_atm[i]) - my);
+    }
+    if (!(sxx > 0.0)) return -1;
+    double c1 = sxy / sxx;
+    *beta = 1.0 + c1;
+    *alpha = exp(my - c1 * mx);
+    return 0;
+}
+
+int or_atm_seed(int model, double beta, int beta_free, int n_par, const double *lb, const double *ub,
+                int n_mat, const double *T, const double *fwd, const int32_t *offs, const double *K,
+                const double *target, double *x0)
+{
+    if (expected_npar(model, beta_free) != n_par || n_mat < 1) return -1;
+    for (int k = 0; k < n_par; ++k) x0[k] = 0.5 * (lb[k] + ub[k]);
+    double *sa = malloc(sizeof(double) * (size_t)n_mat);
+    if (!sa) return -2;
+    int shortest = 0, distinct = 0;
+    for (int i = 0; i < n_mat; ++i) {
+        sa[i] = or_atm_vol(offs[i + 1] - offs[i], K + offs[i], target + offs[i], fwd[i]);
+        if (T[i] < T[shortest]) shortest = i;
+        if (fwd[i] != fwd[0]) distinct = 1;
+    }
+    double b = beta;
+    if (beta_free) {
+        double bb, aa;
+        b = x0[n_par - 1];
+        if (distinct && or_beta_from_atm(n_mat, fwd, sa, &bb, &aa) == 0)
+            b = fmin(fmax(bb, lb[n_par - 1]), ub[n_par - 1]);
+        x0[n_par - 1] = b;
+    }
+    double a = pow(fwd[shortest], 1.0 - b) * sa[shortest];
+    x0[0] = fmin(fmax(a, lb[0]), ub[0]);
+    free(sa);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Case II constraints (Section 5, Technique II): rho(t) in [-1, 1] and      */
 /* nu(t) > 0 for every 0 < t <= T_max.  Each function is (c0 + c1 t) e^(-k t) */
 /* + d; its extrema on [0, T_max] lie at the ends or at the one stationary   */

@@ -84,6 +84,14 @@ double or_objective_mc(int model, int weighting, double beta, int beta_free, int
                        const double *target, int64_t n_paths, int32_t steps_per_year,
                        uint64_t seed);
 
+/* at-the-money start point (Section 3): the market vol at K = f of one row, */
+/* beta and alpha from a log-log fit of (f, sigma_ATM), the start point x0  */
+double or_atm_vol(int m, const double *K, const double *vol, double f);
+int or_beta_from_atm(int n, const double *fwd, const double *sigma_atm, double *beta, double *alpha);
+int or_atm_seed(int model, double beta, int beta_free, int n_par, const double *lb, const double *ub,
+                int n_mat, const double *T, const double *fwd, const int32_t *offs, const double *K,
+                const double *target, double *x0);
+
 /* feasibility of case II functional parameters on (0, T_max] */
 int or_case2_feasible(const double *x, double t_max);
 

@@ -582,6 +582,77 @@ def test_cliquet_limits_are_exact(oracle):
     assert 0.0 < p < 0.06
 
 
+# --- at-the-money start point (Section 3) ----------------------------------------------
+def test_beta_regression_recovers_exact_powers(oracle):
+    """sigma_ATM = alpha f^(beta - 1) exactly (the paper's identity
+    ln sigma_ATM = ln alpha - (1 - beta) ln f) gives beta and alpha back."""
+    f = np.array([0.8, 1.0, 1.7, 2.5, 4.0])
+    for beta, alpha in ((0.7, 0.3), (0.0, 0.02), (1.0, 0.25), (0.45, 1.3)):
+        b, a = oracle.beta_from_atm(f, alpha * f ** (beta - 1.0))
+        assert b == pytest.approx(beta, abs=1e-13) and a == pytest.approx(alpha, rel=1e-13)
+
+
+def test_beta_regression_is_least_squares(oracle):
+    """With noise the estimate is the ordinary least-squares line of ln sigma
+    on ln f (numpy's polyfit) and a mixed-up pairing changes it."""
+    rng = np.random.default_rng(12)
+    f = np.exp(rng.normal(0.0, 0.4, 40))
+    s = 0.3 * f ** (0.6 - 1.0) * np.exp(rng.normal(0.0, 0.02, 40))
+    b, a = oracle.beta_from_atm(f, s)
+    c1, c0 = np.polyfit(np.log(f), np.log(s), 1)
+    assert b == pytest.approx(1.0 + c1, abs=1e-12) and a == pytest.approx(math.exp(c0), rel=1e-12)
+    b2, _ = oracle.beta_from_atm(f, s[::-1])
+    assert abs(b2 - b) > 1e-3
+
+
+def test_atm_vol_interpolates_in_log_strike(oracle):
+    K = np.array([0.8, 0.9, 1.1, 1.2])
+    v = np.array([0.30, 0.25, 0.21, 0.20])
+    f = 1.03
+    u = (math.log(f) - math.log(0.9)) / (math.log(1.1) - math.log(0.9))
+    assert oracle.atm_vol(K, v, f) == pytest.approx(0.25 + u * (0.21 - 0.25), rel=1e-15)
+    assert oracle.atm_vol(K, v, 0.9) == 0.25
+    assert oracle.atm_vol(K, v, 0.5) == 0.30 and oracle.atm_vol(K, v, 2.0) == 0.20
+
+
+@pytest.mark.parametrize("beta", [0.5, 0.7, 1.0])
+def test_atm_seed_alpha_is_hagan_atm_without_the_time_term(oracle, beta):
+    """Hagan's vol at K = f is alpha f^(beta-1) (1 + B T); the seed
+    f^(1-beta) sigma_ATM is therefore alpha (1 + B T), which tends to alpha
+    as T -> 0 (the B T the paper neglects); the other coordinates sit at the
+    box centre."""
+    al, rho, nu = x = [0.25, -0.3, 0.6]
+    f = 1.4
+    lb, ub = inputs.box(inputs.STATIC)
+    B = ((1 - beta) ** 2 * al * al / (24 * f ** (2 - 2 * beta)) + rho * beta * nu * al / (4 * f ** (1 - beta))
+         + (2 - 3 * rho * rho) * nu * nu / 24)
+    for T in (1.0, 0.1, 0.01, 0.001):
+        m = oracle.Market([T], [f], [0, 3], [f * 0.9, f, f * 1.1])
+        m.target = oracle.model_vols(m, oracle.STATIC, x, beta)
+        x0 = oracle.atm_seed(m, oracle.STATIC, lb, ub, beta)
+        assert x0[0] == pytest.approx(al * (1 + B * T), rel=1e-13)
+        np.testing.assert_array_equal(x0[1:], 0.5 * (lb[1:] + ub[1:]))
+
+
+def test_atm_seed_beta_free_across_forwards(oracle):
+    """beta calibrated, maturities with different forwards and short enough
+    that B T is small: the seed's beta is the log-log slope of the ATM vols
+    (here within 1e-3 of the generating beta) and its alpha comes from the
+    shortest maturity; with one common forward beta stays at its box centre."""
+    x = [0.3, -0.2, 0.4, 0.6]
+    fwd = [0.9, 1.2, 1.6, 2.2]
+    T = [0.002, 0.001, 0.003, 0.0015]
+    K = np.concatenate([[f * 0.95, f, f * 1.05] for f in fwd])
+    m = oracle.Market(T, fwd, [0, 3, 6, 9, 12], K)
+    m.target = oracle.model_vols(m, oracle.STATIC, x, 0.0, beta_free=True)
+    lb, ub = inputs.box(inputs.STATIC, beta_free=True)
+    x0 = oracle.atm_seed(m, oracle.STATIC, lb, ub, 0.0, beta_free=True)
+    assert abs(x0[3] - 0.6) < 1e-3 and abs(x0[0] - 0.3) < 1e-3
+    m1 = oracle.Market([0.5, 1.0], [1.0, 1.0], [0, 3, 6], [0.9, 1.0, 1.1] * 2)
+    m1.target = oracle.model_vols(m1, oracle.STATIC, x, 0.0, beta_free=True)
+    assert oracle.atm_seed(m1, oracle.STATIC, lb, ub, 0.0, beta_free=True)[3] == 0.5
+
+
 # --- case II constraint (Section 5, Technique II) -------------------------------------
 def test_case2_feasibility_matches_dense_sampling(oracle):
     """The analytic extremum check agrees with dense sampling of rho(t), nu(t)
