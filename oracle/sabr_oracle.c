@@ -228,6 +228,19 @@ static double fn_nu(const fn_params *q, double t)
     if (q->model == OR_DYN_I) return q->nu0 * exp(-q->b * t);
     return (q->nu0 + q->qnu * t) * exp(-q->b * t) + q->dnu;
 }
+/* The same sums with every term taken by its magnitude: the size of the     */
+/* rounding in fn_rho, fn_nu (eps times this), which where the terms cancel  */
+/* is far above eps times the value.                                         */
+static double fn_rho_mag(const fn_params *q, double t)
+{
+    if (q->model == OR_DYN_I) return fabs(q->rho0) * exp(-q->a * t);
+    return fabs(q->rho0 + q->qrho * t) * exp(-q->a * t) + fabs(q->drho);
+}
+static double fn_nu_mag(const fn_params *q, double t)
+{
+    if (q->model == OR_DYN_I) return fabs(q->nu0) * exp(-q->b * t);
+    return fabs(q->nu0 + q->qnu * t) * exp(-q->b * t) + fabs(q->dnu);
+}
 
 /* Adaptive Gauss-Legendre quadrature: 10- and 20-point rules on an interval, */
 /* bisection until they agree.  Nodes by Newton's method on P_n.             */
@@ -283,23 +296,52 @@ static double integrate(integrand_fn g, const void *ctx, double lo, double hi, d
          + integrate(g, ctx, mid, hi, 0.5 * abs_tol, depth + 1);
 }
 
+/* Integral of g over [lo, hi] to 1e-14 relative, or, where the integral is */
+/* much smaller than its terms (an integrand that changes sign, as nu rho   */
+/* does when rho(t) crosses zero), to 1e-14 of the integral of gm, the same */
+/* integrand with every term by its magnitude.  The rounding of g is about  */
+/* eps gm per value whatever the subinterval, so a purely relative test     */
+/* would bisect to the depth limit wherever the terms of g cancel, and      */
+/* nested inside eta2^2's outer integral that recursion multiplies out.     */
+static double integrate_scaled(integrand_fn g, integrand_fn gm, const void *ctx, double lo, double hi)
+{
+    const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
+    double l1 = 0.0;
+    for (int i = 0; i < 20; ++i) l1 += gl_w20[i] * gm(c + h * gl_x20[i], ctx);
+    return integrate(g, ctx, lo, hi, 1e-14 * l1 * h + 1e-300, 0);
+}
+
 typedef struct { const fn_params *q; double T; } int_ctx;
 
 static double ig_nu1(double t, const void *c)
 { const int_ctx *k = c; double n = fn_nu(k->q, t); return (k->T - t) * (k->T - t) * n * n; }
+static double ig_nu1_mag(double t, const void *c)
+{ const int_ctx *k = c; double n = fn_nu_mag(k->q, t); return (k->T - t) * (k->T - t) * n * n; }
 static double ig_nu2(double t, const void *c)
 { const int_ctx *k = c; double n = fn_nu(k->q, t); return (k->T - t) * t * n * n; }
+static double ig_nu2_mag(double t, const void *c)
+{ const int_ctx *k = c; double n = fn_nu_mag(k->q, t); return (k->T - t) * t * n * n; }
 static double ig_eta1(double t, const void *c)
 { const int_ctx *k = c; return (k->T - t) * fn_nu(k->q, t) * fn_rho(k->q, t); }
+static double ig_eta1_mag(double t, const void *c)
+{ const int_ctx *k = c; return (k->T - t) * fn_nu_mag(k->q, t) * fn_rho_mag(k->q, t); }
 static double ig_nurho(double u, const void *c)
 { const int_ctx *k = c; return fn_nu(k->q, u) * fn_rho(k->q, u); }
+static double ig_nurho_mag(double u, const void *c)
+{ const int_ctx *k = c; return fn_nu_mag(k->q, u) * fn_rho_mag(k->q, u); }
 /* eta2^2's triple integral with the two outer integrals swapped:            */
 /* int_0^T int_0^t g(s) ds dt = int_0^T (T - s) g(s) ds, g = I(s)^2 and      */
 /* I(s) = int_0^s nu(u) rho(u) du computed by its own quadrature.            */
 static double ig_eta2(double s, const void *c)
 {
     const int_ctx *k = c;
-    double I = (s > 0.0) ? integrate(ig_nurho, c, 0.0, s, 1e-300, 0) : 0.0;
+    double I = (s > 0.0) ? integrate_scaled(ig_nurho, ig_nurho_mag, c, 0.0, s) : 0.0;
+    return (k->T - s) * I * I;
+}
+static double ig_eta2_mag(double s, const void *c)
+{
+    const int_ctx *k = c;
+    double I = (s > 0.0) ? integrate_scaled(ig_nurho_mag, ig_nurho_mag, c, 0.0, s) : 0.0;
     return (k->T - s) * I * I;
 }
 
@@ -310,10 +352,10 @@ void or_quad_integrals(int model, double T, const double p[8], double out[4])
     gl_init();
     fn_params q = { p[0], p[1], p[2], p[3], p[4], p[5], p[6], p[7], model };
     int_ctx c = { &q, T };
-    out[0] = 3.0 / (T * T * T) * integrate(ig_nu1, &c, 0.0, T, 1e-300, 0);
-    out[1] = 6.0 / (T * T * T) * integrate(ig_nu2, &c, 0.0, T, 1e-300, 0);
-    out[2] = 2.0 / (T * T) * integrate(ig_eta1, &c, 0.0, T, 1e-300, 0);
-    out[3] = 12.0 / (T * T * T * T) * integrate(ig_eta2, &c, 0.0, T, 1e-300, 0);
+    out[0] = 3.0 / (T * T * T) * integrate_scaled(ig_nu1, ig_nu1_mag, &c, 0.0, T);
+    out[1] = 6.0 / (T * T * T) * integrate_scaled(ig_nu2, ig_nu2_mag, &c, 0.0, T);
+    out[2] = 2.0 / (T * T) * integrate_scaled(ig_eta1, ig_eta1_mag, &c, 0.0, T);
+    out[3] = 12.0 / (T * T * T * T) * integrate_scaled(ig_eta2, ig_eta2_mag, &c, 0.0, T);
 }
 
 /* Case II: the paper obtains eta2^2 only by quadrature (Section 2.2); the   */
