@@ -9,7 +9,7 @@ parameters are drawn uniformly in the box (seeded); the targets are the
 library's double-precision vols at those parameters (noise-free).  The
 requests are prepared once (validated, packed and copied to HBM); a step runs
 the whole calibration on those resident inputs and brings the results back.
-The same step from host arrays (sabr_calibrate) is reported beside it.
+The same step from host arrays (sabr_calibrate_many) is reported beside it.
 
 Prints one JSON line: calibrations/s (value), p50/p99 step latency, formula
 evaluations/s, the annealing kernel's position against the VALU issue peak
@@ -154,7 +154,7 @@ def bench_mc_calibration(S, inputs, ctx, args):
     S.sabr_ctx_enable_timing(ctx, True)
     S.sabr_ctx_timing(ctx, reset=True)
     t = time.perf_counter()
-    res = S.sabr_calibrate(ctx, [req])[0]
+    res = S.sabr_calibrate(ctx, req)
     wall = time.perf_counter() - t
     ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
     m_max = 500
@@ -180,10 +180,10 @@ def bench_dynamic(S, inputs, ctx, args):
                     precision=S.SABR_FP32, n_chains=8192, n_iters=iters, cooling=0.99 ** (1000.0 / iters),
                     seed=0x5AB40001, polish=True)
     S.sabr_ctx_enable_timing(ctx, True)
-    S.sabr_calibrate(ctx, [req])
+    S.sabr_calibrate(ctx, req)
     S.sabr_ctx_timing(ctx, reset=True)
     t = time.perf_counter()
-    res = S.sabr_calibrate(ctx, [req])[0]
+    res = S.sabr_calibrate(ctx, req)
     wall = time.perf_counter() - t
     ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
     pts = 8192 * iters * g.n_obs
@@ -261,7 +261,7 @@ def bench_serving(S, inputs, ctx, args):
         now = time.perf_counter() - t0
         if now < arr:
             time.sleep(arr - now)
-        S.sabr_calibrate(ctx, [r])
+        S.sabr_calibrate(ctx, r)
         lat_1.append(time.perf_counter() - t0 - arr)
         if len(lat_1) % 200 == 0:
             print("one-per-launch %d / %d" % (len(lat_1), len(reqs)), file=sys.stderr, flush=True)
@@ -369,7 +369,7 @@ def main():
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(n_host):
-        host_res = S.sabr_calibrate(ctx, reqs)
+        host_res = S.sabr_calibrate_many(ctx, reqs)
     torch.cuda.synchronize()
     host_s = (time.perf_counter() - t) / max(n_host, 1)
     same = all(np.array_equal(a["x"], b["x"]) and a["f"] == b["f"] for a, b in zip(results, host_res))

@@ -182,23 +182,36 @@ int sabr_ctx_enable_timing(sabr_ctx *ctx, int enable);
 int sabr_ctx_timing(sabr_ctx *ctx, int reset, double *kernel_ms, int64_t *launches,
                     char *kernel_name, size_t name_len);
 
-/* Calibrate n_req independent requests (Section 5, Techniques I and II).
- * Requests with the formula objective run together in one persistent
- * annealing launch per (model, formula, precision) group; Monte Carlo
- * requests run one after the other.  out[n_req] receives one result per
- * request (out[r].status < 0 for a request that failed validation; the call
- * then returns SABR_E_INVAL without running anything).  SABR_E_TIMEOUT: a
- * wait between the workgroups of one request at a level end exceeded its
- * bound (the launch ends early; no result is valid). */
-int sabr_calibrate(sabr_ctx *ctx, int32_t n_req, const sabr_request *reqs, sabr_result *out);
+/* Calibrate one request (Section 5: Technique I with the formula objective,
+ * Technique II with Monte Carlo prices): the grid, model and box, objective,
+ * annealing schedule and, for the Monte Carlo objective, the path settings
+ * (mc may be NULL for the formula objective).  All arguments are host
+ * structs read during the call only.  *out receives the calibrated x, f and
+ * counters; out->status carries the error code on failure.
+ * Errors: SABR_E_INVAL (validation), SABR_E_INFEASIBLE (case II x0 outside
+ * the constraints), SABR_E_BUDGET, SABR_E_NOMEM, SABR_E_DEVICE,
+ * SABR_E_TIMEOUT (a wait between the workgroups of the request at a level end
+ * exceeded its bound; the launch ends early and no result is valid). */
+int sabr_calibrate(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem, const sabr_objspec *obj,
+                   const sabr_sa *sa, const sabr_mc *mc, sabr_result *out);
+
+/* Calibrate n_req independent requests (Section 5, Techniques I and II) in
+ * one call: requests with the formula objective run together in one
+ * persistent annealing launch per (model, formula, precision) group; Monte
+ * Carlo requests run one after the other.  Each result is the one
+ * sabr_calibrate gives for the request alone.  out[n_req] receives one
+ * result per request (out[r].status < 0 for a request that failed
+ * validation; the call then returns SABR_E_INVAL without running anything).
+ * Errors as sabr_calibrate. */
+int sabr_calibrate_many(sabr_ctx *ctx, int32_t n_req, const sabr_request *reqs, sabr_result *out);
 
 /* Prepared batches (Section 5, Technique I): the same calibration as
- * sabr_calibrate for formula-objective requests, split into a setup call
+ * sabr_calibrate_many for formula-objective requests, split into a setup call
  * that validates the requests, packs their grids, schedules and launch plan
  * and copies them to device memory, and a run call that works only on that
  * device-resident data (grid normalisation, annealing, polish) and copies
  * back the results.  Repeated runs repeat the calibration: a run returns
- * bit for bit what sabr_calibrate returns for the same requests.
+ * bit for bit what sabr_calibrate_many returns for the same requests.
  *   sabr_batch_prepare: the requests are read during the call only (the
  *     caller may free them on return).  The batch owns its device memory
  *     (not taken from the context's budget or workspace) until
@@ -235,6 +248,36 @@ int sabr_objective_batch(sabr_ctx *ctx, const sabr_market *market, const sabr_pr
 int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem,
                   const sabr_mc *mc, int32_t precision, double *price, double *std_err);
 
+/* At-the-money start point (Section 3, after eq. "sigma-SABR": ln sigma_ATM
+ * = ln alpha - (1 - beta) ln f, from the formula at K = f without its
+ * T-correction).  market->target holds market vols (> 0; the strikes of each
+ * row increasing); x0[n_par] (host) receives: alpha = f_s^(1 - beta)
+ * sigma_ATM,s at the shortest maturity s (lowest index on ties), where
+ * sigma_ATM of a row is its vol at K = f linear in ln K between the strikes
+ * around f (the end strike's vol beyond the row); with beta calibrated and
+ * at least two distinct forwards, beta = 1 + the slope of the least-squares
+ * line of ln sigma_ATM on ln f over the maturities (otherwise the fixed beta,
+ * or the centre of its box); alpha and beta clamped to the box, every other
+ * coordinate at the box centre.  problem->x0 is ignored.  The result can be
+ * passed back as problem->x0 of a calibration.
+ * Errors: SABR_E_INVAL (validation), SABR_E_DEVICE. */
+int sabr_atm_seed(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem, double *x0);
+
+/* Cliquet price (Section 6, eqs. "eq_cliquet" and "eq:cliquet_global") by
+ * the Monte Carlo paths of sabr_mc_price at the parameters problem->x0
+ * (required), forward f0 > 0 today, discount factor disc > 0 at expiry.
+ * reset_T[n_reset] (years, n_reset >= 2) are the reset dates d_1 < ... < d_D,
+ * each read at step max(1, floor(d_i / dt)) of the path grid (the steps must
+ * increase).  Payoff per path: the returns R_i = (F(d_i) - F(d_{i-1})) /
+ * F(d_{i-1}), i = 2..D, each clamped to [local_floor, local_cap], summed,
+ * and the sum clamped to [global_floor, global_cap] (floors <= caps); a
+ * return from an absorbed forward is -1.  *price = disc * mean payoff,
+ * *std_err its standard error (std_err may be NULL).  Host outputs.
+ * Errors: SABR_E_INVAL (validation), SABR_E_DEVICE. */
+int sabr_mc_cliquet(sabr_ctx *ctx, const sabr_problem *problem, double f0, double disc, int32_t n_reset,
+                    const double *reset_T, double local_floor, double local_cap, double global_floor,
+                    double global_cap, const sabr_mc *mc, int32_t precision, double *price, double *std_err);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of calibration requests (Section 5, Techniques
  * I and II, run for many independent requests at once).
@@ -254,8 +297,9 @@ int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *
  * Supported requests: FP32 precision, fixed beta, and either the static
  * Hagan formula (<= 256 chains), the dynamic case I formula (<= 512 chains)
  * or the static Monte Carlo objective (<= 64 chains, <= 600 options);
- * grids up to 1024 points and 32 maturities.  Others: SABR_E_INVAL (use
- * sabr_calibrate).  A request's result depends only on the request (its
+ * grids up to 1024 points and 32 maturities; Monte Carlo requests of at
+ * most 32768 paths.  Others: SABR_E_INVAL (use sabr_calibrate).  A
+ * request's result depends only on the request (its
  * random words are keyed by its seed and chain ids, its sums run in a fixed
  * order): it is the same alone, in any mix and for any quantum length.
  *
@@ -269,10 +313,13 @@ typedef struct sabr_server sabr_server;
  * SABR_E_NOMEM, SABR_E_DEVICE (graph capture failed). */
 int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes, int32_t quantum_levels,
                        sabr_server **out);
-/* Copies the request (the caller may free its arrays on return) and queues
- * it; *ticket identifies its result.  Errors: SABR_E_INVAL (invalid or
- * unsupported request), SABR_E_BUDGET (larger than the whole budget). */
-int sabr_server_submit(sabr_server *srv, const sabr_request *req, uint64_t *ticket);
+/* Copies the request (the caller may free its arrays on return; mc may be
+ * NULL for the formula objective) and queues it; *ticket identifies its
+ * result.  Errors: SABR_E_INVAL (invalid or unsupported request, including a
+ * Monte Carlo request of more than 32768 paths), SABR_E_BUDGET (larger than
+ * the whole budget). */
+int sabr_server_submit(sabr_server *srv, const sabr_market *market, const sabr_problem *problem,
+                       const sabr_objspec *obj, const sabr_sa *sa, const sabr_mc *mc, uint64_t *ticket);
 /* Returns up to max finished requests (tickets[], res[], and, if not NULL,
  * latency_s[] = completion minus submission in seconds), waiting up to
  * timeout_us for the first one.  res[i].status is SABR_OK or

@@ -264,6 +264,92 @@ const void *polish_kernel_ptr(int model, int formula, bool bfree) {
     return v < 0 ? nullptr : tab[v];
 }
 
+// ---------------------------------------------------------------------------
+// Start point from the at-the-money vols (Section 3, after eq. "sigma-SABR"):
+// at K = f the static formulas give ln sigma_ATM = ln alpha - (1 - beta) ln f
+// (up to the T-correction), so beta is one plus the slope of the least-squares
+// line of ln sigma_ATM against ln f over the maturities, and alpha =
+// f^(1 - beta) sigma_ATM.  sigma_ATM of a row is its market vol at K = f, linear
+// in ln K between the two strikes around f (the end strike's vol beyond the
+// row); beta is fitted only when it is calibrated and the forwards differ
+// (else the fixed beta, or the centre of its box); alpha is taken at the
+// shortest maturity (lowest index on ties), where the neglected T-correction
+// is smallest; both are clamped to the box and every other coordinate is the
+// box centre.  One wave: lane i % 64 takes maturity i, sums meet in a
+// butterfly.
+// ---------------------------------------------------------------------------
+__device__ double atm_vol_of_row(int m, const double *K, const double *v, double f) {
+#pragma clang fp contract(off)
+    if (f <= K[0]) return v[0];
+    if (f >= K[m - 1]) return v[m - 1];
+    int j = 0;
+    while (K[j + 1] < f) ++j;   // strikes of a row increase
+    const double u = (log(f) - log(K[j])) / (log(K[j + 1]) - log(K[j]));
+    return v[j] + u * (v[j + 1] - v[j]);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(64) atm_seed_kernel(AtmDesc d, const double *T, const double *fwd,
+                                                      const int32_t *offs, const double *K, const double *vol,
+                                                      double *x0) {
+#pragma clang fp contract(off)
+    const int lane = threadIdx.x;
+    double sx = 0.0, sy = 0.0, tmin = __builtin_inf();
+    int imin = 0x7fffffff;
+    bool distinct = false;
+    for (int i = lane; i < d.n_mat; i += 64) {
+        const double sa = atm_vol_of_row(offs[i + 1] - offs[i], K + offs[i], vol + offs[i], fwd[i]);
+        sx += log(fwd[i]);
+        sy += log(sa);
+        if (T[i] < tmin) {
+            tmin = T[i];
+            imin = i;
+        }
+        distinct |= fwd[i] != fwd[0];
+    }
+    // shortest maturity, lowest index on ties
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double t2 = __shfl_xor(tmin, o, 64);
+        const int i2 = __shfl_xor(imin, o, 64);
+        if (t2 < tmin || (t2 == tmin && i2 < imin)) {
+            tmin = t2;
+            imin = i2;
+        }
+    }
+    const double n = (double)d.n_mat;
+    const double mx = wave_sum(sx) / n, my = wave_sum(sy) / n;
+    double sxx = 0.0, sxy = 0.0;
+    for (int i = lane; i < d.n_mat; i += 64) {
+        const double sa = atm_vol_of_row(offs[i + 1] - offs[i], K + offs[i], vol + offs[i], fwd[i]);
+        const double dx = log(fwd[i]) - mx;
+        sxx += dx * dx;
+        sxy += dx * (log(sa) - my);
+    }
+    sxx = wave_sum(sxx);
+    sxy = wave_sum(sxy);
+    const bool any_distinct = __ballot(distinct) != 0;
+    if (lane != 0) return;
+    const int np = d.n_par;
+    double b = d.beta;
+    if (d.beta_free) {
+        b = 0.5 * (d.lb[np - 1] + d.ub[np - 1]);
+        if (any_distinct && d.n_mat >= 2 && sxx > 0.0) b = fmin(fmax(1.0 + sxy / sxx, d.lb[np - 1]), d.ub[np - 1]);
+    }
+    const int s = imin;
+    const double sa = atm_vol_of_row(offs[s + 1] - offs[s], K + offs[s], vol + offs[s], fwd[s]);
+    const double a = pow(fwd[s], 1.0 - b) * sa;
+    for (int k = 0; k < np; ++k) x0[k] = 0.5 * (d.lb[k] + d.ub[k]);
+    x0[0] = fmin(fmax(a, d.lb[0]), d.ub[0]);
+    if (d.beta_free) x0[np - 1] = b;
+}
+
+const void *atm_seed_kernel_ptr() { return (const void *)atm_seed_kernel; }
 const void *prepare_points_kernel_ptr() { return (const void *)prepare_points_kernel; }
 const void *prepare_mats_kernel_ptr() { return (const void *)prepare_mats_kernel; }
 

@@ -109,6 +109,89 @@ __global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, cons
 }
 
 // ---------------------------------------------------------------------------
+// Cliquet (Section 6, eqs. "eq_cliquet" and "eq:cliquet_global") on the paths
+// of the pricing kernel above, one parameter set: lane = path.  The forward
+// is read at the reset dates d_1 < ... < d_D (step max(1, floor(d_i / dt)),
+// as for the European maturities); each return R_i = (F_{d_i} - F_{d_{i-1}}) /
+// F_{d_{i-1}}, i = 2..D, is clamped to [local floor, local cap] and the
+// returns are summed; the sum is clamped to [global floor, global cap] (the
+// printed max/min of the global payoff read so that the floor is the lower
+// limit).  A return from an absorbed (zero) forward is -1.  Payoffs and their
+// squares are summed over the wave in double and per wave in LDS; the
+// workgroup writes its two sums once, and mc_price_finalize turns them into
+// the discounted mean and its standard error.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256) mc_cliquet_kernel(CliqDesc d, const int32_t *reset_steps, double *part_s,
+                                                        double *part_q) {
+    extern __shared__ unsigned char smem[];
+    StepC<R> *st = reinterpret_cast<StepC<R> *>(smem);
+    double *acc_s = reinterpret_cast<double *>(smem + sizeof(StepC<R>) * ((d.m_max + 1) / 2 * 2));
+    double *acc_q = acc_s + 4;
+    for (int s = threadIdx.x; s < d.m_max; s += blockDim.x) st[s] = step_coeffs<R>(d.model, d.x, s * d.dt, d.dt);
+    if (threadIdx.x < 4) acc_s[threadIdx.x] = acc_q[threadIdx.x] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const R bm1 = (R)(d.beta - 1.0);
+    const R hd = (R)(d.dt / (2.0 * kLn2));
+    const R xabs = (R)kLog2Abs;
+    const R A0 = (R)(log2(d.x[0]) + (d.beta - 1.0) * log2(d.f0));
+    const R f0 = (R)d.f0;
+    const R lf = (R)d.local_floor, lc = (R)d.local_cap, gf = (R)d.global_floor, gc = (R)d.global_cap;
+    const int64_t n_tiles = (d.n_paths + 255) / 256;
+    for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const int64_t path = tile * 256 + threadIdx.x;
+        const bool active = path < d.n_paths;
+        R X = 0, A = A0, Fp = 0, sum = 0;
+        int next = 0;
+        uint4 w = make_uint4(0, 0, 0, 0);
+        for (int s = 0; s < d.m_max; ++s) {
+            if ((s & 1) == 0) w = philox4x32_10(make_uint4((uint32_t)path, (uint32_t)(s >> 1), 0u, 2u), d.key0, d.key1);
+            const R u1 = MC<R>::unit((s & 1) ? w.z : w.x);
+            const R u2 = MC<R>::unit((s & 1) ? w.w : w.y);
+            R z1, z2;
+            MC<R>::normals(u1, u2, z1, z2);
+            const StepC<R> c = st[s];
+            const R vh = MC<R>::exp2_(fma(bm1, fmax(X, xabs), A));
+            A = fma(c.nz, z1, A + c.nd);
+            const R w2 = fma(c.rz, z1, c.rp * z2);
+            const R Xn = fma(vh, fma(-hd, vh, w2), X);
+            X = (Xn < xabs) ? -(R)__builtin_inff() : Xn;
+            if (next < d.n_reset && reset_steps[next] == s + 1) {
+                const R F = f0 * MC<R>::exp2_(X);
+                if (next > 0) {
+                    const R ret = Fp > (R)0 ? (F - Fp) / Fp : (R)-1;
+                    sum += fmax(fmin(ret, lc), lf);
+                }
+                Fp = F;
+                ++next;
+            }
+        }
+        const double v = active ? (double)fmax(gf, fmin(gc, sum)) : 0.0;
+        double vs = v, vq = v * v;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            vs += __shfl_xor(vs, off, 64);
+            vq += __shfl_xor(vq, off, 64);
+        }
+        if (lane == 0) {
+            acc_s[wave] += vs;
+            acc_q[wave] += vq;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0, q = 0.0;
+        for (int wv = 0; wv < 4; ++wv) {
+            s += acc_s[wv];
+            q += acc_q[wv];
+        }
+        part_s[blockIdx.x] = s;
+        part_q[blockIdx.x] = q;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Common-random-number kernel for the Monte Carlo objective: lane = one
 // parameter set (chain), a whole wave follows the same path.  The normals of
 // 64 steps are drawn cooperatively (lane l draws step s0 + l) and broadcast
@@ -166,6 +249,13 @@ const void *mc_price_kernel_ptr(bool fp32) {
     return fp32 ? (const void *)mc_price_kernel<float> : (const void *)mc_price_kernel<double>;
 }
 const void *mc_price_finalize_ptr() { return (const void *)mc_price_finalize; }
+const void *mc_cliquet_kernel_ptr(bool fp32) {
+    return fp32 ? (const void *)mc_cliquet_kernel<float> : (const void *)mc_cliquet_kernel<double>;
+}
+size_t mc_cliquet_smem_bytes(bool fp32, int m_max) {
+    const size_t st = (fp32 ? sizeof(StepC<float>) : sizeof(StepC<double>)) * (size_t)((m_max + 1) / 2 * 2);
+    return st + 8 * sizeof(double);
+}
 // variant: 0 = the production layout (kCrnPaths, kCrnLdsNormals); 1..8 =
 // (1, 2, 4, 8 paths per lane) x (scalar broadcast, LDS broadcast); 9 = 16
 // paths per lane with LDS broadcast; for tuning.

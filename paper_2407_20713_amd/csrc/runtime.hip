@@ -83,7 +83,7 @@ enum Slot {
     S_K, S_FWDP, S_BETAP, S_FORMP, S_WGHTP, S_TARGET, S_LFK, S_LKF, S_P1, S_Z, S_Q1, S_Q2, S_SW, S_ROW,
     S_T, S_FWD, S_BETAM, S_LNF, S_F1, S_OFFS, S_REQ, S_WGREQ, S_SCHED_G, S_SCHED_H, S_CAND,
     S_BEST, S_ACC, S_ERR, S_EVALS, S_POLREQ, S_X, S_F, S_MODEL, S_MSTEPS, S_MOFFS, S_DISC, S_OBSROW,
-    S_PART, S_PARTQ, S_E2, S_PRICE, S_SE, S_Y, S_CX, S_CF, S_BX, S_BF, S_FY, S_MCSTATE, S_NSLOTS
+    S_PART, S_PARTQ, S_E2, S_PRICE, S_SE, S_Y, S_CX, S_CF, S_BX, S_BF, S_FY, S_MCSTATE, S_RESET, S_NSLOTS
 };
 
 // Start of an API call that computes: with a caller workspace, the buffers
@@ -361,7 +361,7 @@ bool case2_ok_host(const double *x, double tmax) {
         const double v0 = c0 + d, v1 = (c0 + c1 * tmax) * std::exp(-k * tmax) + d;
         lo = std::min(v0, v1);
         hi = std::max(v0, v1);
-        if (k > 0.0 && c1 != 0.0) {
+        if (k != 0.0 && c1 != 0.0) {   // interior extremum, either sign of k
             const double ts = 1.0 / k - c0 / c1;
             if (ts > 0.0 && ts < tmax) {
                 const double v = (c0 + c1 * ts) * std::exp(-k * ts) + d;
@@ -1173,7 +1173,7 @@ int sabr_ctx_timing(sabr_ctx *c, int reset, double *kernel_ms, int64_t *launches
     return SABR_OK;
 }
 
-int sabr_calibrate(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_result *out) {
+int sabr_calibrate_many(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_result *out) {
     if (!c) return SABR_E_INVAL;
     begin_call(c);
     if (n_req < 1 || !reqs || !out) return fail(c, SABR_E_INVAL, "need n_req >= 1 and non-NULL arrays");
@@ -1199,6 +1199,23 @@ int sabr_calibrate(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_re
     return SABR_OK;
 }
 
+int sabr_calibrate(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem, const sabr_objspec *obj,
+                   const sabr_sa *sa, const sabr_mc *mc, sabr_result *out) {
+    if (!c) return SABR_E_INVAL;
+    if (!market || !problem || !obj || !sa || !out)
+        return fail(c, SABR_E_INVAL, "market, problem, objspec, sa and out must not be NULL");
+    if (obj->kind == SABR_OBJ_MC && !mc) return fail(c, SABR_E_INVAL, "the Monte Carlo objective needs mc settings");
+    sabr_request q;
+    std::memset(&q, 0, sizeof q);
+    q.market = *market;
+    q.problem = *problem;
+    q.obj = *obj;
+    q.sa = *sa;
+    if (mc) q.mc = *mc;
+    const int rc = sabr_calibrate_many(c, 1, &q, out);
+    return (rc == SABR_E_INVAL && out->status < 0) ? out->status : rc;   // e.g. SABR_E_INFEASIBLE
+}
+
 int sabr_batch_prepare(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sabr_batch **out) {
     if (!c) return SABR_E_INVAL;
     if (!out) return fail(c, SABR_E_INVAL, "out is NULL");
@@ -1209,7 +1226,7 @@ int sabr_batch_prepare(sabr_ctx *c, int32_t n_req, const sabr_request *reqs, sab
     for (int r = 0; r < n_req; ++r)
         if (reqs[r].obj.kind == SABR_OBJ_MC)
             return fail(c, SABR_E_INVAL, "request %d uses the Monte Carlo objective; a prepared batch holds formula "
-                                         "requests only (use sabr_calibrate)", r);
+                                         "requests only (use sabr_calibrate_many)", r);
     std::vector<sabr_result> tmp(n_req);
     int rc;
     if ((rc = validate_requests(c, n_req, reqs, tmp.data()))) return rc;
@@ -1396,6 +1413,119 @@ int sabr_mc_price(sabr_ctx *c, const sabr_market *market, const sabr_problem *pr
         return rc;
     HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
     if (std_err) HIPCHK(c, hipMemcpyAsync(std_err, se, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
+    return sync_and_account(c);
+}
+
+int sabr_atm_seed(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem, double *x0) {
+    if (!c) return SABR_E_INVAL;
+    begin_call(c);
+    c->err.clear();
+    hipSetDevice(c->device);
+    int rc;
+    if ((rc = check_problem(c, problem, true)) || (rc = check_market(c, market, true, false, SABR_W_ABSOLUTE)))
+        return rc;
+    if (!x0) return fail(c, SABR_E_INVAL, "x0 is NULL");
+    const sabr_market &m = *market;
+    for (int i = 0; i < m.n_mat; ++i)
+        for (int j = m.offs[i]; j < m.offs[i + 1]; ++j) {
+            if (!(m.target[j] > 0)) return fail(c, SABR_E_INVAL, "target[%d] must be a positive vol", j);
+            if (j > m.offs[i] && !(m.K[j] > m.K[j - 1]))
+                return fail(c, SABR_E_INVAL, "strikes of maturity %d must increase", i);
+        }
+    const int n_obs = m.offs[m.n_mat];
+    std::vector<double> T(m.T, m.T + m.n_mat), fwd(m.fwd, m.fwd + m.n_mat), K(m.K, m.K + n_obs),
+        tg(m.target, m.target + n_obs);
+    std::vector<int32_t> offs(m.offs, m.offs + m.n_mat + 1);
+    double *dT, *dF, *dK, *dV;
+    int32_t *dO;
+    void *dx;
+    if ((rc = upload(c, S_T, T, &dT)) || (rc = upload(c, S_FWD, fwd, &dF)) || (rc = upload(c, S_K, K, &dK)) ||
+        (rc = upload(c, S_TARGET, tg, &dV)) || (rc = upload(c, S_OFFS, offs, &dO)) ||
+        (rc = get_buf(c, S_X, sizeof(double) * kMaxPar, &dx)))
+        return rc;
+    AtmDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.n_mat = m.n_mat;
+    d.n_par = problem->n_par;
+    d.beta_free = problem->beta_free ? 1 : 0;
+    d.beta = problem->beta;
+    for (int k = 0; k < problem->n_par; ++k) {
+        d.lb[k] = problem->lb[k];
+        d.ub[k] = problem->ub[k];
+    }
+    void *args[] = {&d, &dT, &dF, &dO, &dK, &dV, &dx};
+    if ((rc = launch(c, false, "atm_seed_kernel", atm_seed_kernel_ptr(), dim3(1), dim3(64), args, 0))) return rc;
+    HIPCHK(c, hipMemcpyAsync(x0, dx, sizeof(double) * problem->n_par, hipMemcpyDeviceToHost, c->stream));
+    return sync_and_account(c);
+}
+
+int sabr_mc_cliquet(sabr_ctx *c, const sabr_problem *problem, double f0, double disc, int32_t n_reset,
+                    const double *reset_T, double local_floor, double local_cap, double global_floor,
+                    double global_cap, const sabr_mc *mc, int32_t precision, double *price, double *std_err) {
+    if (!c) return SABR_E_INVAL;
+    begin_call(c);
+    c->err.clear();
+    hipSetDevice(c->device);
+    int rc;
+    if ((rc = check_problem(c, problem, false))) return rc;
+    if (!problem->x0) return fail(c, SABR_E_INVAL, "problem->x0 (the parameters) is NULL");
+    if ((rc = check_mc(c, mc))) return rc;
+    if (precision != SABR_FP32 && precision != SABR_FP64) return fail(c, SABR_E_INVAL, "bad precision");
+    if (!price) return fail(c, SABR_E_INVAL, "price is NULL");
+    if (!(f0 > 0) || !std::isfinite(f0) || !(disc > 0) || !std::isfinite(disc))
+        return fail(c, SABR_E_INVAL, "f0 and disc must be finite and > 0");
+    if (n_reset < 2 || !reset_T) return fail(c, SABR_E_INVAL, "a cliquet needs at least two reset dates");
+    if (!(local_floor <= local_cap) || !(global_floor <= global_cap) || !std::isfinite(local_floor) || !std::isfinite(local_cap) ||
+        !std::isfinite(global_floor) || !std::isfinite(global_cap))
+        return fail(c, SABR_E_INVAL, "floors must be finite and not above their caps");
+    std::vector<int32_t> rs(n_reset);
+    for (int i = 0; i < n_reset; ++i) {
+        if (!(reset_T[i] > 0) || !std::isfinite(reset_T[i])) return fail(c, SABR_E_INVAL, "reset_T[%d] must be > 0", i);
+        rs[i] = n_steps(reset_T[i], mc->steps_per_year);
+        if (i > 0 && rs[i] <= rs[i - 1])
+            return fail(c, SABR_E_INVAL, "reset dates must fall on increasing steps of 1/%d y", mc->steps_per_year);
+    }
+    CliqDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.model = problem->model;
+    d.n_reset = n_reset;
+    d.m_max = rs[n_reset - 1];
+    d.n_paths = mc->n_paths;
+    d.dt = 1.0 / (double)mc->steps_per_year;
+    d.f0 = f0;
+    const int NP = problem->n_par;
+    d.beta = problem->beta_free ? problem->x0[NP - 1] : problem->beta;
+    for (int k = 0; k < base_npar(problem->model); ++k) d.x[k] = problem->x0[k];
+    d.local_floor = local_floor;
+    d.local_cap = local_cap;
+    d.global_floor = global_floor;
+    d.global_cap = global_cap;
+    d.key0 = (uint32_t)(mc->seed & 0xffffffffu);
+    d.key1 = (uint32_t)(mc->seed >> 32);
+    const bool fp32 = precision == SABR_FP32;
+    const int64_t tiles = (mc->n_paths + 255) / 256;
+    const int n_blocks = (int)std::min<int64_t>(tiles, 2048);
+    int32_t *drs, *drow;
+    double *ddisc;
+    void *ps, *pq, *pr, *se;
+    std::vector<int32_t> row0(1, 0);
+    std::vector<double> dv(1, disc);
+    if ((rc = upload(c, S_RESET, rs, &drs)) || (rc = upload(c, S_OBSROW, row0, &drow)) ||
+        (rc = upload(c, S_DISC, dv, &ddisc)) || (rc = get_buf(c, S_PART, sizeof(double) * (size_t)n_blocks, &ps)) ||
+        (rc = get_buf(c, S_PARTQ, sizeof(double) * (size_t)n_blocks, &pq)) ||
+        (rc = get_buf(c, S_PRICE, sizeof(double), &pr)) || (rc = get_buf(c, S_SE, sizeof(double), &se)))
+        return rc;
+    const void *fn = mc_cliquet_kernel_ptr(fp32);
+    const size_t smem = mc_cliquet_smem_bytes(fp32, d.m_max);
+    if ((rc = set_smem(c, fn, smem))) return rc;
+    void *a1[] = {&d, &drs, &ps, &pq};
+    if ((rc = launch(c, true, "mc_cliquet_kernel", fn, dim3(n_blocks), dim3(256), a1, smem))) return rc;
+    int one = 1, nblk = n_blocks;
+    int64_t np = mc->n_paths;
+    void *a2[] = {&one, &nblk, &np, &ps, &pq, &drow, &ddisc, &pr, &se};
+    if ((rc = launch(c, false, "mc_price_finalize", mc_price_finalize_ptr(), dim3(1), dim3(64), a2, 0))) return rc;
+    HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (std_err) HIPCHK(c, hipMemcpyAsync(std_err, se, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     return sync_and_account(c);
 }
 

@@ -342,14 +342,16 @@ __device__ inline void case2_integrals(const FnII &p, double T, int n_panel, dou
 }
 
 // Case II feasibility on (0, t_max]: each function is (c0 + c1 t) e^(-k t) + d,
-// whose extrema lie at the ends or at t* = 1/k - c0/c1.
+// whose extrema lie at the ends or at t* = 1/k - c0/c1 (the derivative
+// e^(-k t) (c1 - k (c0 + c1 t)) vanishes there for either sign of k, so
+// growing exponentials are checked as well as decaying ones).
 __device__ __forceinline__ void fn_range(double c0, double c1, double k, double d, double tmax,
                                          double &lo, double &hi) {
     const double v0 = c0 + d;
     const double v1 = fma(c1, tmax, c0) * exp(-k * tmax) + d;
     lo = fmin(v0, v1);
     hi = fmax(v0, v1);
-    if (k > 0.0 && c1 != 0.0) {
+    if (k != 0.0 && c1 != 0.0) {
         const double ts = 1.0 / k - c0 / c1;
         if (ts > 0.0 && ts < tmax) {
             const double v = fma(c1, ts, c0) * exp(-k * ts) + d;

@@ -209,7 +209,7 @@ struct ModelEval {
             } else {
                 FnII fp{y[1], y[2], y[3], y[4], y[5], y[6], y[7], y[8]};
                 const double Td = (double)rw.T;
-                const double kmax = fmax(fmax(y[3], y[4]), 1.0);
+                const double kmax = fmax(fmax(fabs(y[3]), fabs(y[4])), 1.0);   // growing rates too
                 int np = (int)ceil(Td * kmax);
                 np = np < 1 ? 1 : (np > 64 ? 64 : np);
                 double ints[4];
@@ -295,7 +295,11 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
     ModelEval<MODEL, FORMULA, R, BFREE, P> ev;
     if (!ev.init(y, beta_fixed, t_max)) return __builtin_inf();
     bool bad = false;
-    if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION && !BFREE && sizeof(R) == 4 && !WRITE) {
+    // The hot loop folds nu / ln 2 into the maturity factor and divides by
+    // nu for the island bound, so a vanishing nu (the box allows nu = 0, where
+    // z / x(z) = 1 and the vol has its finite limit) takes the generic loop.
+    if constexpr (MODEL == MODEL_STATIC && FORMULA != F_EXPANSION && !BFREE && sizeof(R) == 4 && !WRITE)
+    if (ev.nu >= 1e-20f) {
         // float hot loop of the static z-form formulas, two points per step so
         // that their dependency chains interleave.  With zr = z - rho and
         // q = sqrt(zr^2 + 1 - rho^2) (= sqrt(1 - 2 rho z + z^2)), x(z) / ln 2 is

@@ -42,7 +42,25 @@ struct McSaState {
     double best_x[kMaxPar];
 };
 
+// At-the-money start point of one grid (one wave).
+struct AtmDesc {
+    int32_t n_mat, n_par, beta_free, pad;
+    double beta;
+    double lb[kMaxPar], ub[kMaxPar];
+};
+
+// Cliquet on the Monte Carlo paths of one parameter set (lane = path).
+struct CliqDesc {
+    int32_t model, n_reset, m_max, pad;
+    int64_t n_paths;
+    double dt, f0, beta;
+    double x[kMaxPar];
+    double local_floor, local_cap, global_floor, global_cap;
+    uint32_t key0, key1;
+};
+
 // Kernel handles (the kernels are templates instantiated in the .hip files).
+const void *atm_seed_kernel_ptr();
 const void *prepare_points_kernel_ptr();
 const void *prepare_mats_kernel_ptr();
 const void *objective_kernel_ptr(int model, int formula, bool fp32, bool bfree);
@@ -54,6 +72,8 @@ size_t sa_smem_fixed_bytes();
 
 const void *mc_price_kernel_ptr(bool fp32);
 const void *mc_price_finalize_ptr();
+const void *mc_cliquet_kernel_ptr(bool fp32);
+size_t mc_cliquet_smem_bytes(bool fp32, int m_max);
 const void *mc_crn_kernel_ptr(int model, int variant);
 const void *mc_crn_direct_kernel_ptr(int model);
 int mc_crn_direct_paths();   // paths per block of the direct kernel

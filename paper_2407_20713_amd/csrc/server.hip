@@ -661,11 +661,19 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
     return SABR_OK;
 }
 
-int sabr_server_submit(sabr_server *s, const sabr_request *req, uint64_t *ticket) {
-    if (!s || !req || !ticket) return SABR_E_INVAL;
+int sabr_server_submit(sabr_server *s, const sabr_market *market, const sabr_problem *problem,
+                       const sabr_objspec *obj, const sabr_sa *sa, const sabr_mc *mc, uint64_t *ticket) {
+    if (!s || !market || !problem || !obj || !sa || !ticket) return SABR_E_INVAL;
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->device_error) return fail(s->ctx, SABR_E_DEVICE, "server stopped after a device error");
-    const sabr_request &q = *req;
+    if (obj->kind == SABR_OBJ_MC && !mc) return fail(s->ctx, SABR_E_INVAL, "the Monte Carlo objective needs mc settings");
+    sabr_request q;
+    std::memset(&q, 0, sizeof q);
+    q.market = *market;
+    q.problem = *problem;
+    q.obj = *obj;
+    q.sa = *sa;
+    if (mc) q.mc = *mc;
     int rc = check_request(s->ctx, q);
     if (rc) return rc;
     const int kind = slot_kind(q);
@@ -680,6 +688,10 @@ int sabr_server_submit(sabr_server *s, const sabr_request *req, uint64_t *ticket
     if (q.sa.n_chains > cap) return fail(s->ctx, SABR_E_INVAL, "at most %d chains per request of this kind", cap);
     if (n_pts > kSlotMaxPts || q.market.n_mat > kSlotMaxMat || (kind == KIND_MC && n_pts > kSlotMaxMcObs))
         return fail(s->ctx, SABR_E_INVAL, "grid too large for a serving slot");
+    // each lane of a path block adds its block's payoffs in float: at most
+    // 256 per block (the bound of the float partial sums), kMcPBlocks blocks
+    if (kind == KIND_MC && q.mc.n_paths > (int64_t)256 * kMcPBlocks)
+        return fail(s->ctx, SABR_E_INVAL, "a served Monte Carlo request takes at most %d paths", 256 * kMcPBlocks);
     Owned *o = new Owned();
     o->kind = kind;
     const sabr_market &m = q.market;

@@ -26,8 +26,9 @@ SABR_FP64, SABR_FP32 = 0, 1
 
 EXPORTED = ["sabr_ctx_create", "sabr_ctx_destroy", "sabr_ctx_last_error", "sabr_ctx_set_workspace",
             "sabr_ctx_enable_timing",
-            "sabr_ctx_timing", "sabr_calibrate", "sabr_batch_prepare", "sabr_batch_run", "sabr_batch_destroy",
-            "sabr_objective_batch", "sabr_mc_price",
+            "sabr_ctx_timing", "sabr_calibrate", "sabr_calibrate_many", "sabr_batch_prepare", "sabr_batch_run",
+            "sabr_batch_destroy",
+            "sabr_objective_batch", "sabr_mc_price", "sabr_atm_seed", "sabr_mc_cliquet",
             "sabr_server_create", "sabr_server_submit", "sabr_server_poll", "sabr_server_cancel",
             "sabr_server_stats", "sabr_server_destroy"]
 
@@ -103,7 +104,10 @@ def lib():
         L.sabr_ctx_set_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
         L.sabr_ctx_enable_timing.argtypes = [C.c_void_p, C.c_int]
         L.sabr_ctx_timing.argtypes = [C.c_void_p, C.c_int, _D, C.POINTER(C.c_int64), C.c_char_p, C.c_size_t]
-        L.sabr_calibrate.argtypes = [C.c_void_p, C.c_int32, C.POINTER(sabr_request), C.POINTER(sabr_result)]
+        L.sabr_calibrate.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem),
+                                     C.POINTER(sabr_objspec), C.POINTER(sabr_sa), C.POINTER(sabr_mc),
+                                     C.POINTER(sabr_result)]
+        L.sabr_calibrate_many.argtypes = [C.c_void_p, C.c_int32, C.POINTER(sabr_request), C.POINTER(sabr_result)]
         L.sabr_batch_prepare.argtypes = [C.c_void_p, C.c_int32, C.POINTER(sabr_request), C.POINTER(C.c_void_p)]
         L.sabr_batch_run.argtypes = [C.c_void_p, C.POINTER(sabr_result)]
         L.sabr_batch_destroy.argtypes = [C.c_void_p]
@@ -113,8 +117,14 @@ def lib():
                                            C.c_void_p, C.c_void_p]
         L.sabr_mc_price.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem),
                                     C.POINTER(sabr_mc), C.c_int32, _D, _D]
+        L.sabr_atm_seed.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem), _D]
+        L.sabr_mc_cliquet.argtypes = [C.c_void_p, C.POINTER(sabr_problem), C.c_double, C.c_double, C.c_int32, _D,
+                                      C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(sabr_mc),
+                                      C.c_int32, _D, _D]
         L.sabr_server_create.argtypes = [C.c_void_p, C.c_int32, C.c_size_t, C.c_int32, C.POINTER(C.c_void_p)]
-        L.sabr_server_submit.argtypes = [C.c_void_p, C.POINTER(sabr_request), C.POINTER(C.c_uint64)]
+        L.sabr_server_submit.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem),
+                                         C.POINTER(sabr_objspec), C.POINTER(sabr_sa), C.POINTER(sabr_mc),
+                                         C.POINTER(C.c_uint64)]
         L.sabr_server_poll.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_uint64),
                                        C.POINTER(sabr_result), _D, C.POINTER(C.c_int32)]
         L.sabr_server_cancel.argtypes = [C.c_void_p, C.c_uint64]
@@ -258,12 +268,23 @@ class Request:
         return sabr_request(self.market.c(), self.problem.c(), self.obj, self.sa, self.mc)
 
 
-def sabr_calibrate(ctx, requests):
-    """Calibrate a list of Request; returns a list of dicts (x, f, ...)."""
+def sabr_calibrate(ctx, request):
+    """Calibrate one Request; returns a dict (x, f, f_before_polish, n_evals, n_accept, status)."""
+    m, p = request.market.c(), request.problem.c()
+    out = (sabr_result * 1)()
+    rc = lib().sabr_calibrate(ctx.h, C.byref(m), C.byref(p), C.byref(request.obj), C.byref(request.sa),
+                              C.byref(request.mc), out)
+    if rc != SABR_OK:
+        raise SabrError(rc, lib().sabr_ctx_last_error(ctx.h).decode())
+    return _results([request], out)[0]
+
+
+def sabr_calibrate_many(ctx, requests):
+    """Calibrate a list of Request in one call; returns a list of dicts."""
     n = len(requests)
     arr = (sabr_request * n)(*[r.c() for r in requests])
     out = (sabr_result * n)()
-    rc = lib().sabr_calibrate(ctx.h, n, arr, out)
+    rc = lib().sabr_calibrate_many(ctx.h, n, arr, out)
     if rc != SABR_OK:
         raise SabrError(rc, lib().sabr_ctx_last_error(ctx.h).decode())
     return _results(requests, out)
@@ -368,6 +389,27 @@ def sabr_mc_price(ctx, market, problem, n_paths, steps_per_year=250, seed=0, pre
     return price, se
 
 
+def sabr_atm_seed(ctx, market, problem):
+    """At-the-money start point from market.target (market vols); returns x0."""
+    x0 = np.zeros(problem.n_par)
+    m, p = market.c(), problem.c()
+    ctx.check(lib().sabr_atm_seed(ctx.h, C.byref(m), C.byref(p), _dp(x0)))
+    return x0
+
+
+def sabr_mc_cliquet(ctx, problem, f0, reset_T, local_floor, local_cap, global_floor, global_cap, n_paths,
+                    steps_per_year=250, seed=0, disc=1.0, precision=SABR_FP32):
+    """Cliquet price at problem.x0 on the Monte Carlo paths; returns (price, std_err)."""
+    rt = _f64(reset_T)
+    price, se = C.c_double(), C.c_double()
+    p = problem.c()
+    mc = sabr_mc(n_paths, steps_per_year, seed)
+    ctx.check(lib().sabr_mc_cliquet(ctx.h, C.byref(p), f0, disc, len(rt), _dp(rt), local_floor, local_cap,
+                                    global_floor, global_cap, C.byref(mc), precision, C.byref(price),
+                                    C.byref(se)))
+    return price.value, se.value
+
+
 # --- serving -------------------------------------------------------------------
 class Server:
     """Handle of a sabr_server (continuous batching of calibration requests)."""
@@ -379,8 +421,9 @@ class Server:
 
     def submit(self, request):
         t = C.c_uint64()
-        r = request.c()
-        self.ctx.check(lib().sabr_server_submit(self.h, C.byref(r), C.byref(t)))
+        m, p = request.market.c(), request.problem.c()
+        self.ctx.check(lib().sabr_server_submit(self.h, C.byref(m), C.byref(p), C.byref(request.obj),
+                                                C.byref(request.sa), C.byref(request.mc), C.byref(t)))
         return t.value
 
     def poll(self, max_n=64, timeout_us=0):

@@ -357,7 +357,7 @@ def test_sa_fp64_matches_oracle_trajectory(S, ctx, oracle, n_chains):
     say("sa fp64 chains", n_chains)
     x_true = np.array([0.2, -0.3, 0.5])
     req, m, lb, ub = smile_request(S, oracle, x_true, 1e-4, S.SABR_FP64, n_chains, 200, 0x5AB10001)
-    got = S.sabr_calibrate(ctx, [req])[0]
+    got = S.sabr_calibrate(ctx, req)
     ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, n_chains, 200, 0x5AB10001)
     say("gpu", got["x"], got["f"], got["n_accept"], "oracle", ref["x"], ref["f"], ref["n_accept"])
     assert got["n_accept"] == ref["n_accept"]
@@ -372,13 +372,13 @@ def test_sa_single_smile_recovery_fp32_and_fp64(S, ctx, oracle):
     x_true = np.array([0.2, -0.3, 0.5])
     r64, m, lb, ub = smile_request(S, oracle, x_true, 1e-4, S.SABR_FP64, 64, 1000, 0x5AB10001)
     r32, _, _, _ = smile_request(S, oracle, x_true, 1e-4, S.SABR_FP32, 64, 1000, 0x5AB10001)
-    g64, g32 = S.sabr_calibrate(ctx, [r64, r32])
+    g64, g32 = S.sabr_calibrate_many(ctx, [r64, r32])
     ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, 64, 1000, 0x5AB10001, cooling=0.99)
     say("fp64", g64["x"], "fp32", g32["x"], "oracle", ref["x"])
     np.testing.assert_allclose(g64["x"], ref["x"], atol=1e-3)
     np.testing.assert_allclose(g32["x"], ref["x"], atol=1e-3)
     p32, _, _, _ = smile_request(S, oracle, x_true, 0.0, S.SABR_FP32, 64, 1000, 7, polish=True)
-    gp = S.sabr_calibrate(ctx, [p32])[0]
+    gp = S.sabr_calibrate(ctx, p32)
     np.testing.assert_allclose(gp["x"], x_true, atol=1e-3)
     assert gp["f"] <= gp["f_before_polish"] * (1 + 1e-6) + 1e-12
 
@@ -390,7 +390,7 @@ def test_polish_matches_oracle(S, ctx, oracle, noise_sd):
     x_true = np.array([0.2, -0.3, 0.5])
     req, m, lb, ub = smile_request(S, oracle, x_true, noise_sd, S.SABR_FP64, 64, 300, 17, polish=True,
                                    noise_seed=9)
-    got = S.sabr_calibrate(ctx, [req])[0]
+    got = S.sabr_calibrate(ctx, req)
     ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, 64, 300, 17, polish=True)
     say("polish gpu", got["x"], got["f"], "oracle", ref["x"], ref["f"])
     assert got["f_before_polish"] == pytest.approx(ref["f_before_polish"], rel=1e-12)
@@ -408,9 +408,9 @@ def test_sa_batch_equals_alone(S, ctx, oracle):
         r, _, _, _ = smile_request(S, oracle, np.array(xt), 1e-4, S.SABR_FP32, (256, 320, 1100, 2048)[k], 300,
                                    100 + k)
         reqs.append(r)
-    together = S.sabr_calibrate(ctx, reqs)
+    together = S.sabr_calibrate_many(ctx, reqs)
     for r, t in zip(reqs, together):
-        alone = S.sabr_calibrate(ctx, [r])[0]
+        alone = S.sabr_calibrate(ctx, r)
         assert np.array_equal(alone["x"], t["x"]) and alone["f"] == t["f"] and alone["n_accept"] == t["n_accept"]
 
 
@@ -423,7 +423,7 @@ def test_sa_dynamic_case1_fp64_trajectory(S, ctx, oracle):
     lb, ub = inputs.box(inputs.DYN_I)
     req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_DYN_I, 0.7, lb, ub),
                     precision=S.SABR_FP64, n_chains=64, n_iters=100, seed=5)
-    got = S.sabr_calibrate(ctx, [req])[0]
+    got = S.sabr_calibrate(ctx, req)
     ref = oracle.calibrate(m, oracle.DYN_I, lb, ub, 0.7, 64, 100, 5)
     assert got["n_accept"] == ref["n_accept"]
     np.testing.assert_allclose(got["x"], ref["x"], atol=1e-12)
@@ -441,7 +441,7 @@ def test_sa_mc_objective_trajectory(S, ctx, oracle):
     req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
                     kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=8,
                     n_iters=20, seed=3, n_paths=512, steps_per_year=250, mc_seed=4242)
-    got = S.sabr_calibrate(ctx, [req])[0]
+    got = S.sabr_calibrate(ctx, req)
     ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, 8, 20, 3, weighting=oracle.RELATIVE,
                            objective=oracle.OBJ_MC, mc_paths=512, mc_steps_per_year=250, mc_seed=4242)
     say("mc sa gpu", got, "oracle", ref)
@@ -488,7 +488,7 @@ def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model, n
                       ("8x2", {"SABR_LANES_PER_CHAIN": "8", "SABR_ROW_SPLIT": "2"})):
         c = _ctx_with(S, env) if env else ctx
         say("wide lanes", model, name)
-        runs[name] = S.sabr_calibrate(c, [req])[0]
+        runs[name] = S.sabr_calibrate(c, req)
         if env:
             c.close()
     base = runs["one"]
@@ -513,10 +513,10 @@ def test_large_batch_runs_in_resident_parts(S, ctx, oracle):
         tgt = oracle.model_vols(m, inputs.DYN_I, xt, 0.7)
         reqs.append(S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_DYN_I, 0.7, lb, ub),
                               precision=S.SABR_FP32, n_chains=1024, n_iters=20, seed=500 + k))
-    together = S.sabr_calibrate(ctx, reqs)
+    together = S.sabr_calibrate_many(ctx, reqs)
     assert all(r["status"] == 0 for r in together)
     for i in (0, 21, 39):
-        alone = S.sabr_calibrate(ctx, [reqs[i]])[0]
+        alone = S.sabr_calibrate(ctx, reqs[i])
         assert np.array_equal(alone["x"], together[i]["x"]) and alone["f"] == together[i]["f"]
         assert alone["n_accept"] == together[i]["n_accept"]
 
@@ -533,7 +533,7 @@ def test_caller_workspace_gives_identical_results(S, ctx, oracle):
     mk = S.Market.from_grid(g, target=np.full(6, 0.2))
 
     def run(c):
-        r = S.sabr_calibrate(c, [req])[0]
+        r = S.sabr_calibrate(c, req)
         f, mod = S.sabr_objective_batch(c, mk, S.Problem(S.SABR_STATIC, 0.7), X, precision=S.SABR_FP32,
                                         want_model=True)
         p, se = S.sabr_mc_price(c, S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7, x0=[0.2, -0.3, 0.5]),
@@ -551,10 +551,10 @@ def test_caller_workspace_gives_identical_results(S, ctx, oracle):
             assert np.array_equal(a, b)
     S.sabr_ctx_set_workspace(c, ws, 4096)
     with pytest.raises(S.SabrError) as e:
-        S.sabr_calibrate(c, [req])
+        S.sabr_calibrate(c, req)
     assert e.value.code == S.SABR_E_BUDGET
     S.sabr_ctx_set_workspace(c, None)
-    assert np.array_equal(S.sabr_calibrate(c, [req])[0]["x"], ref[0]["x"])
+    assert np.array_equal(S.sabr_calibrate(c, req)["x"], ref[0]["x"])
     c.close()
 
 
@@ -571,7 +571,7 @@ def test_mc_objective_calibration_recovers_truth(S, ctx):
     req = S.Request(S.Market.from_grid(g, target=tgt[0]), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
                     kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=256,
                     n_iters=150, seed=5, n_paths=2048, steps_per_year=50, mc_seed=11)
-    r = S.sabr_calibrate(ctx, [req])[0]
+    r = S.sabr_calibrate(ctx, req)
     say("mc recovery", r["x"][:3], r["f"])
     assert r["status"] == 0
     np.testing.assert_allclose(r["x"][:3], xt, atol=1e-3)
@@ -598,7 +598,7 @@ def test_sa_float_objective_at_result_matches_oracle(S, ctx, oracle, n_chains, f
     req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.6, lb, ub),
                     formula=formula, weighting=weighting, precision=S.SABR_FP32, n_chains=n_chains,
                     n_iters=300, chain_len=10, cooling=0.99 ** (1000.0 / 300), seed=0xF10A7 + formula)
-    got = S.sabr_calibrate(ctx, [req])[0]
+    got = S.sabr_calibrate(ctx, req)
     x = np.asarray(got["x"][:3])
     ref_f = oracle.objective_formula(m, oracle.STATIC, x, 0.6, False, formula, weighting)
     ref_v = oracle.model_vols(m, oracle.STATIC, x, 0.6, False, formula)
@@ -627,7 +627,7 @@ def test_sa_never_accepts_negative_vols(S, ctx, oracle, prec, n_chains):
     tgt = np.full(3, 0.3)
     req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.5, lb, ub),
                     precision=prec, n_chains=n_chains, n_iters=40, chain_len=10, seed=0x5EED)
-    got = S.sabr_calibrate(ctx, [req])[0]
+    got = S.sabr_calibrate(ctx, req)
     say("negative vols", prec, n_chains, got["n_accept"], got["f"])
     assert got["n_accept"] == 0
     assert not np.isfinite(got["f"])
@@ -652,7 +652,7 @@ def test_sa_degenerate_sizes_follow_oracle(S, ctx, oracle, n_chains, n_iters, ch
     req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
                     precision=S.SABR_FP64, n_chains=n_chains, n_iters=n_iters, chain_len=chain_len,
                     cooling=cooling, seed=0x77 + n_chains)
-    got = S.sabr_calibrate(ctx, [req])[0]
+    got = S.sabr_calibrate(ctx, req)
     ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, n_chains, n_iters, 0x77 + n_chains,
                            chain_len=chain_len, cooling=cooling)
     say("degenerate", n_chains, n_iters, chain_len, n_strikes, got["n_accept"], ref["n_accept"])
@@ -669,7 +669,7 @@ def test_grid_too_large_for_lds_is_rejected(S, ctx):
     req = S.Request(S.Market.from_grid(g, target=np.full(g.n_obs, 0.2)), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
                     precision=S.SABR_FP64, n_chains=64, n_iters=10)
     with pytest.raises(S.SabrError) as e:
-        S.sabr_calibrate(ctx, [req])
+        S.sabr_calibrate(ctx, req)
     assert e.value.code == S.SABR_E_INVAL
 
 
@@ -681,17 +681,17 @@ def test_polish_grid_too_large_is_rejected_before_annealing(S, ctx):
     lb, ub = inputs.box(inputs.STATIC)
     mk = S.Market.from_grid(g, target=np.full(g.n_obs, 0.2))
     with pytest.raises(S.SabrError) as e:
-        S.sabr_calibrate(ctx, [S.Request(mk, S.Problem(S.SABR_STATIC, 0.7, lb, ub), precision=S.SABR_FP32,
-                                         n_chains=64, n_iters=10, polish=True)])
+        S.sabr_calibrate(ctx, S.Request(mk, S.Problem(S.SABR_STATIC, 0.7, lb, ub), precision=S.SABR_FP32,
+                                        n_chains=64, n_iters=10, polish=True))
     assert e.value.code == S.SABR_E_INVAL
-    r = S.sabr_calibrate(ctx, [S.Request(mk, S.Problem(S.SABR_STATIC, 0.7, lb, ub), precision=S.SABR_FP32,
-                                         n_chains=64, n_iters=10, polish=False)])[0]
+    r = S.sabr_calibrate(ctx, S.Request(mk, S.Problem(S.SABR_STATIC, 0.7, lb, ub), precision=S.SABR_FP32,
+                                        n_chains=64, n_iters=10, polish=False))
     assert r["status"] == 0 and np.isfinite(r["f"])
 
 
 def test_prepared_batch_repeats_calibrate_bitwise(S, ctx, oracle):
     """A prepared batch (inputs uploaded once) returns, run after run, exactly
-    what sabr_calibrate returns for the same requests: mixed models,
+    what sabr_calibrate_many returns for the same requests: mixed models,
     precisions and polish, and a group large enough to run in resident parts."""
     g = inputs.dynamic_surface()
     m = omkt(oracle, g)
@@ -706,7 +706,7 @@ def test_prepared_batch_repeats_calibrate_bitwise(S, ctx, oracle):
     for prec, pol in ((S.SABR_FP32, True), (S.SABR_FP64, False)):
         req, _, _, _ = smile_request(S, oracle, np.array([0.2, -0.3, 0.5]), 1e-4, prec, 512, 300, 41, polish=pol)
         reqs.append(req)
-    ref = S.sabr_calibrate(ctx, reqs)
+    ref = S.sabr_calibrate_many(ctx, reqs)
     b = S.sabr_batch_prepare(ctx, reqs)
     try:
         for rep in range(2):
@@ -717,7 +717,7 @@ def test_prepared_batch_repeats_calibrate_bitwise(S, ctx, oracle):
                 assert a["f_before_polish"] == e["f_before_polish"] and a["n_accept"] == e["n_accept"], (rep, r)
                 assert a["n_evals"] == e["n_evals"], (rep, r)
             # work of the context between runs leaves the batch unchanged
-            S.sabr_calibrate(ctx, reqs[-1:])
+            S.sabr_calibrate_many(ctx, reqs[-1:])
     finally:
         S.sabr_batch_destroy(b)
 
@@ -747,11 +747,11 @@ def test_exchange_wait_bound_reports_timeout(S, ctx, oracle, n_chains):
     c = _ctx_with(S, {"SABR_EXCHANGE_SPINS": "0"})
     try:
         with pytest.raises(S.SabrError) as e:
-            S.sabr_calibrate(c, [req])
+            S.sabr_calibrate(c, req)
         assert e.value.code == S.SABR_E_TIMEOUT
     finally:
         c.close()
-    r = S.sabr_calibrate(ctx, [req])[0]
+    r = S.sabr_calibrate(ctx, req)
     assert r["status"] == 0 and np.isfinite(r["f"])
 
 

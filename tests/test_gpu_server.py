@@ -180,3 +180,93 @@ def test_monte_carlo_lds_classes_alone_equals_mix(S, ctx, oracle):
         assert a["status"] == 0 and b["status"] == 0
         assert np.array_equal(a["x"], b["x"]) and a["f"] == b["f"] and a["n_accept"] == b["n_accept"]
         assert np.isfinite(a["f"]) and a["f"] >= 0.0
+
+
+def test_second_wave_joins_running_requests(S, ctx, oracle):
+    """Continuous batching: with few slots and room in the memory budget for
+    about two requests, a second wave submitted while the first is on the
+    device (quanta already run) is admitted as slots and memory free up, and
+    every result of both waves is bitwise the one the request gets alone."""
+    trace = [t for t in small_trace(60, 21) if t.kind == "static"][:8]
+    reqs = [build_request(S, oracle, t, 128, 1500)[0] for t in trace]
+    srv = S.Server(ctx, max_slots=4, hbm_budget_bytes=2 * 1024 * 1024, quantum_levels=5)
+    first = [srv.submit(r) for r in reqs[:4]]
+    t0 = time.time()
+    while srv.stats()["quanta"] == 0 and time.time() - t0 < 60:
+        time.sleep(0.001)
+    st = srv.stats()
+    say("before second wave", st)
+    assert st["quanta"] > 0 and st["completed"] < 4
+    second = [srv.submit(r) for r in reqs[4:]]
+    got = {}
+    t0 = time.time()
+    while len(got) < len(reqs) and time.time() - t0 < 120:
+        for t, res, lat in srv.poll(16, 200000):
+            got[t] = res
+    st = srv.stats()
+    srv.close()
+    say("after", st)
+    assert len(got) == len(reqs)
+    for r, t in zip(reqs, first + second):
+        srv1 = S.Server(ctx, max_slots=4, quantum_levels=5)
+        alone = run_all(srv1, [r])[0][0]
+        srv1.close()
+        b = got[t]
+        assert alone["status"] == 0 and b["status"] == 0
+        assert np.array_equal(alone["x"], b["x"]) and alone["f"] == b["f"] and alone["n_accept"] == b["n_accept"]
+
+
+def test_served_dynamic_request_matches_oracle_calibration(S, ctx, oracle):
+    """A dynamic (case I) request served in FP32 with polish reaches the
+    oracle's polished FP64 calibration to 1e-3."""
+    trace = small_trace(40, 6)
+    t = next(x for x in trace if x.kind == "dynamic" and x.grid.n_mat >= 3)
+    req, m, tgt = build_request(S, oracle, t, 256, 2000)
+    srv = S.Server(ctx, max_slots=8, quantum_levels=10)
+    res = run_all(srv, [req])[0][0]
+    srv.close()
+    m.target = tgt
+    lb, ub = inputs.box(inputs.DYN_I)
+    ref = oracle.calibrate(m, oracle.DYN_I, lb, ub, 0.7, 256, 2000, t.seed, polish=True)
+    say("served dynamic", res["x"][:5], res["f"], "oracle", ref["x"], ref["f"])
+    np.testing.assert_allclose(res["x"][:5], ref["x"], atol=1e-3)
+    assert res["f"] <= ref["f"] * (1 + 1e-6) + 1e-14
+
+
+def test_served_monte_carlo_request_follows_oracle(S, ctx, oracle):
+    """A Monte Carlo request served on the slot kernels (8 chains x 20
+    iterations x 512 common paths) takes the oracle's accept decisions."""
+    g = inputs.make_grid([0.25, 0.5], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0)
+    m = oracle.Market(g.T, g.fwd, g.offs, g.K, disc=g.disc)
+    tgt, _ = oracle.mc_prices(m, oracle.STATIC, [0.2, -0.3, 0.5], 0.7, 512, 250, 4242)
+    m.target = tgt
+    lb, ub = inputs.box(inputs.STATIC)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=8,
+                    n_iters=20, seed=3, n_paths=512, steps_per_year=250, mc_seed=4242)
+    srv = S.Server(ctx, max_slots=16, quantum_levels=3)
+    res = run_all(srv, [req])[0][0]
+    srv.close()
+    ref = oracle.calibrate(m, oracle.STATIC, lb, ub, 0.7, 8, 20, 3, weighting=oracle.RELATIVE,
+                           objective=oracle.OBJ_MC, mc_paths=512, mc_steps_per_year=250, mc_seed=4242)
+    say("served mc", res["x"][:3], res["n_accept"], "oracle", ref["x"], ref["n_accept"])
+    assert res["status"] == 0 and res["n_accept"] == ref["n_accept"]
+    np.testing.assert_allclose(res["x"][:3], ref["x"], atol=1e-12)
+    assert abs(res["f"] - ref["f"]) <= 1e-3 * ref["f"]
+
+
+def test_served_monte_carlo_path_limit(S, ctx, oracle):
+    """A served Monte Carlo request adds at most 256 payoffs per lane in
+    float: more than 256 x 128 paths is refused (sabr_calibrate takes it)."""
+    g = inputs.make_grid([0.25], [np.exp(np.linspace(-0.2, 0.2, 3))], f0=1.0)
+    lb, ub = inputs.box(inputs.STATIC)
+    srv = S.Server(ctx, max_slots=16, quantum_levels=3)
+    req = S.Request(S.Market.from_grid(g, target=np.full(3, 0.05)), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=8,
+                    n_iters=4, seed=3, n_paths=32769, steps_per_year=50, mc_seed=1)
+    with pytest.raises(S.SabrError) as e:
+        srv.submit(req)
+    assert e.value.code == S.SABR_E_INVAL
+    req.mc.n_paths = 32768
+    srv.submit(req)
+    srv.close()
