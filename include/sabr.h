@@ -248,6 +248,25 @@ int sabr_objective_batch(sabr_ctx *ctx, const sabr_market *market, const sabr_pr
 int sabr_mc_price(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem,
                   const sabr_mc *mc, int32_t precision, double *price, double *std_err);
 
+/* sabr_mc_price without device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, validation and
+ * results as sabr_mc_price (bit for bit), but every device buffer of the call
+ * (grid, workgroup partial sums, outputs) lives in one static array of 17 MiB
+ * that each device holds from the loading of the library until the process
+ * ends, and the caller's host arrays are copied to it directly (no pinned
+ * staging buffer): the call makes no hipMalloc, hipHostMalloc or hipFree.
+ * Limit: the call needs about 32 KiB x n_obs of partial sums (2048
+ * workgroups, reached at 2^19 paths) plus 48 bytes per option and maturity,
+ * so up to 512 options at any path count (more with fewer paths); larger
+ * calls return SABR_E_BUDGET.  Every call on a device shares that device's
+ * array: calls that overlap on one device (two host threads, or two contexts
+ * on different streams) race and must be serialised by the caller.
+ * Errors: as sabr_mc_price, plus SABR_E_BUDGET (too large for the array) and
+ * SABR_E_DEVICE (the array's device address could not be obtained). */
+int sabr_mc_price_noalloc(sabr_ctx *ctx, const sabr_market *market, const sabr_problem *problem,
+                          const sabr_mc *mc, int32_t precision, double *price, double *std_err);
+
 /* At-the-money start point (Section 3, after eq. "sigma-SABR": ln sigma_ATM
  * = ln alpha - (1 - beta) ln f, from the formula at K = f without its
  * T-correction).  market->target holds market vols (> 0; the strikes of each

@@ -88,6 +88,25 @@ __global__ void __launch_bounds__(256) mc_price_kernel(McDesc d, const int32_t *
     }
 }
 
+// Path grid of a Monte Carlo pricing call from the raw grid in device
+// memory: step of each maturity max(1, floor(T dt^-1 + 1e-9)) (the host's
+// rule, in the same double arithmetic), maturity row of each option, and the
+// discount factors (1 where none are given).  One thread per option.
+__global__ void mc_grid_kernel(int n_mat, const double *T, const int32_t *offs, int spy, const double *disc_in,
+                               int32_t *msteps, int32_t *obsrow, double *disc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n_mat) {
+        const int m = (int)floor(T[j] * (double)spy + 1e-9);
+        msteps[j] = m < 1 ? 1 : m;
+        disc[j] = disc_in ? disc_in[j] : 1.0;
+    }
+    if (j < offs[n_mat]) {
+        int i = 0;
+        while (offs[i + 1] <= j) ++i;
+        obsrow[j] = i;
+    }
+}
+
 // Sums of the workgroup partials in a fixed order: price = disc * S / N and
 // its standard error.
 __global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, const double *part_s,
@@ -249,6 +268,7 @@ const void *mc_price_kernel_ptr(bool fp32) {
     return fp32 ? (const void *)mc_price_kernel<float> : (const void *)mc_price_kernel<double>;
 }
 const void *mc_price_finalize_ptr() { return (const void *)mc_price_finalize; }
+const void *mc_grid_kernel_ptr() { return (const void *)mc_grid_kernel; }
 const void *mc_cliquet_kernel_ptr(bool fp32) {
     return fp32 ? (const void *)mc_cliquet_kernel<float> : (const void *)mc_cliquet_kernel<double>;
 }

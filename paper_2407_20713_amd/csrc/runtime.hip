@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,39 @@ struct sabr_ctx {
     unsigned char *stage = nullptr;
     size_t stage_bytes = 0, stage_used = 0;
 };
+
+// ---------------------------------------------------------------------------
+// Device memory of sabr_mc_price_noalloc: a file-scope array that each device
+// holds from the loading of the library until the process ends.  In host
+// code its name is only a stand-in: the address of each device's copy comes
+// from hipGetSymbolAddress, taken once per device when the first context on
+// that device is created, and only that address is handed to kernels and
+// copies.  Layout of one call (256-byte aligned pieces): the workgroup
+// partial sums and sums of squares (2048 x n_obs doubles each), price and
+// standard error, strikes, discount factors, maturities, row offsets,
+// maturity steps and option rows.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)17 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch[kMaxDevices];      // device address of each device's copy
+static hipError_t g_scratch_err[kMaxDevices];
+
+// With `device` current: look up its copy of the scratch array once.
+static void scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) {
+        hipGetLastError();
+        g_scratch_err[device] = e;
+        return;
+    }
+    g_scratch[device] = static_cast<unsigned char *>(ptr);
+}
 
 namespace {
 
@@ -1067,6 +1101,7 @@ int sabr_ctx_create(int device, size_t hbm_budget_bytes, void *stream, sabr_ctx 
         delete c;
         return SABR_E_DEVICE;
     }
+    scratch_setup(device);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
         delete c;
@@ -1414,6 +1449,87 @@ int sabr_mc_price(sabr_ctx *c, const sabr_market *market, const sabr_problem *pr
     HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
     if (std_err) HIPCHK(c, hipMemcpyAsync(std_err, se, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
     return sync_and_account(c);
+}
+
+int sabr_mc_price_noalloc(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem, const sabr_mc *mc,
+                         int32_t precision, double *price, double *std_err) {
+    if (!c) return SABR_E_INVAL;
+    c->err.clear();
+    hipSetDevice(c->device);
+    int rc;
+    if ((rc = check_problem(c, problem, false))) return rc;
+    if (!problem->x0) return fail(c, SABR_E_INVAL, "problem->x0 (the parameters) is NULL");
+    if ((rc = check_market(c, market, false, true, SABR_W_ABSOLUTE))) return rc;
+    if ((rc = check_mc(c, mc))) return rc;
+    if (precision != SABR_FP32 && precision != SABR_FP64) return fail(c, SABR_E_INVAL, "bad precision");
+    if (!price) return fail(c, SABR_E_INVAL, "price is NULL");
+    const int n_mat = market->n_mat, n_obs = market->offs[n_mat];
+    int m_max = 0, prev = 0;
+    for (int i = 0; i < n_mat; ++i) {
+        const int m = n_steps(market->T[i], mc->steps_per_year);
+        if (m < prev) return fail(c, SABR_E_INVAL, "Monte Carlo grids must list maturities in increasing order");
+        prev = m;
+        m_max = std::max(m_max, m);
+    }
+    unsigned char *base = c->device < kMaxDevices ? g_scratch[c->device] : nullptr;
+    if (!base)
+        return fail(c, SABR_E_DEVICE, "no address for the static scratch array on device %d: %s", c->device,
+                    hipGetErrorString(c->device < kMaxDevices ? g_scratch_err[c->device] : hipErrorInvalidDevice));
+    const int64_t tiles = (mc->n_paths + 255) / 256;
+    const int n_blocks = (int)std::min<int64_t>(tiles, 2048);
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_ps = 0, o_pq = o_ps + al(sizeof(double) * (size_t)n_blocks * n_obs);
+    const size_t o_pr = o_pq + al(sizeof(double) * (size_t)n_blocks * n_obs);
+    const size_t o_se = o_pr + al(sizeof(double) * n_obs), o_K = o_se + al(sizeof(double) * n_obs);
+    const size_t o_disc = o_K + al(sizeof(double) * n_obs), o_T = o_disc + al(sizeof(double) * n_mat);
+    const size_t o_din = o_T + al(sizeof(double) * n_mat), o_offs = o_din + al(sizeof(double) * n_mat);
+    const size_t o_ms = o_offs + al(sizeof(int32_t) * (n_mat + 1)), o_row = o_ms + al(sizeof(int32_t) * n_mat);
+    const size_t total = o_row + al(sizeof(int32_t) * n_obs);
+    if (total > kScratchBytes)
+        return fail(c, SABR_E_BUDGET, "the call needs %zu bytes of device scratch, the static array has %zu", total,
+                    kScratchBytes);
+    double *ps = (double *)(base + o_ps), *pq = (double *)(base + o_pq), *pr = (double *)(base + o_pr);
+    double *se = (double *)(base + o_se), *K = (double *)(base + o_K), *disc = (double *)(base + o_disc);
+    double *T = (double *)(base + o_T), *din = market->disc ? (double *)(base + o_din) : nullptr;
+    int32_t *offs = (int32_t *)(base + o_offs), *ms = (int32_t *)(base + o_ms), *orow = (int32_t *)(base + o_row);
+    // the caller's host arrays go straight to the device (no staging buffer)
+    HIPCHK(c, hipMemcpyAsync(T, market->T, sizeof(double) * n_mat, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(offs, market->offs, sizeof(int32_t) * (n_mat + 1), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(K, market->K, sizeof(double) * n_obs, hipMemcpyHostToDevice, c->stream));
+    if (din) HIPCHK(c, hipMemcpyAsync(din, market->disc, sizeof(double) * n_mat, hipMemcpyHostToDevice, c->stream));
+    int spy = mc->steps_per_year, nm = n_mat;
+    void *ag[] = {&nm, &T, &offs, &spy, &din, &ms, &orow, &disc};
+    if ((rc = launch(c, false, "mc_grid_kernel", mc_grid_kernel_ptr(), dim3((n_obs + 255) / 256), dim3(256), ag, 0)))
+        return rc;
+    McDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.model = problem->model;
+    d.n_mat = n_mat;
+    d.n_obs = n_obs;
+    d.m_max = m_max;
+    d.n_paths = mc->n_paths;
+    d.dt = 1.0 / (double)mc->steps_per_year;
+    d.f0 = market->fwd[0];
+    const int NP = problem->n_par;
+    d.beta = problem->beta_free ? problem->x0[NP - 1] : problem->beta;
+    for (int k = 0; k < base_npar(problem->model); ++k) d.x[k] = problem->x0[k];
+    d.key0 = (uint32_t)(mc->seed & 0xffffffffu);
+    d.key1 = (uint32_t)(mc->seed >> 32);
+    const bool fp32 = precision == SABR_FP32;
+    const void *fn = mc_price_kernel_ptr(fp32);
+    const size_t smem = mc_price_smem_bytes(fp32, m_max, n_obs);
+    if ((rc = set_smem(c, fn, smem))) return rc;
+    void *a1[] = {&d, &ms, &offs, &K, &ps, &pq};
+    if ((rc = launch(c, false, "mc_price_kernel", fn, dim3(n_blocks), dim3(256), a1, smem))) return rc;
+    int no = n_obs, nblk = n_blocks;
+    int64_t np = mc->n_paths;
+    void *a2[] = {&no, &nblk, &np, &ps, &pq, &orow, &disc, &pr, &se};
+    if ((rc = launch(c, false, "mc_price_finalize", mc_price_finalize_ptr(), dim3((n_obs + 255) / 256), dim3(256), a2, 0)))
+        return rc;
+    HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
+    if (std_err) HIPCHK(c, hipMemcpyAsync(std_err, se, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return SABR_OK;
 }
 
 int sabr_atm_seed(sabr_ctx *c, const sabr_market *market, const sabr_problem *problem, double *x0) {

@@ -72,6 +72,7 @@ size_t sa_smem_fixed_bytes();
 
 const void *mc_price_kernel_ptr(bool fp32);
 const void *mc_price_finalize_ptr();
+const void *mc_grid_kernel_ptr();
 const void *mc_cliquet_kernel_ptr(bool fp32);
 size_t mc_cliquet_smem_bytes(bool fp32, int m_max);
 const void *mc_crn_kernel_ptr(int model, int variant);

@@ -28,7 +28,7 @@ EXPORTED = ["sabr_ctx_create", "sabr_ctx_destroy", "sabr_ctx_last_error", "sabr_
             "sabr_ctx_enable_timing",
             "sabr_ctx_timing", "sabr_calibrate", "sabr_calibrate_many", "sabr_batch_prepare", "sabr_batch_run",
             "sabr_batch_destroy",
-            "sabr_objective_batch", "sabr_mc_price", "sabr_atm_seed", "sabr_mc_cliquet",
+            "sabr_objective_batch", "sabr_mc_price", "sabr_mc_price_noalloc", "sabr_atm_seed", "sabr_mc_cliquet",
             "sabr_server_create", "sabr_server_submit", "sabr_server_poll", "sabr_server_cancel",
             "sabr_server_stats", "sabr_server_destroy"]
 
@@ -117,6 +117,8 @@ def lib():
                                            C.c_void_p, C.c_void_p]
         L.sabr_mc_price.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem),
                                     C.POINTER(sabr_mc), C.c_int32, _D, _D]
+        L.sabr_mc_price_noalloc.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem),
+                                            C.POINTER(sabr_mc), C.c_int32, _D, _D]
         L.sabr_atm_seed.argtypes = [C.c_void_p, C.POINTER(sabr_market), C.POINTER(sabr_problem), _D]
         L.sabr_mc_cliquet.argtypes = [C.c_void_p, C.POINTER(sabr_problem), C.c_double, C.c_double, C.c_int32, _D,
                                       C.c_double, C.c_double, C.c_double, C.c_double, C.POINTER(sabr_mc),
@@ -386,6 +388,17 @@ def sabr_mc_price(ctx, market, problem, n_paths, steps_per_year=250, seed=0, pre
     m, p = market.c(), problem.c()
     mc = sabr_mc(n_paths, steps_per_year, seed)
     ctx.check(lib().sabr_mc_price(ctx.h, C.byref(m), C.byref(p), C.byref(mc), precision, _dp(price), _dp(se)))
+    return price, se
+
+
+def sabr_mc_price_noalloc(ctx, market, problem, n_paths, steps_per_year=250, seed=0, precision=SABR_FP32):
+    """sabr_mc_price on the library's static device scratch (no device allocation)."""
+    price = np.zeros(market.n_obs)
+    se = np.zeros(market.n_obs)
+    m, p = market.c(), problem.c()
+    mc = sabr_mc(n_paths, steps_per_year, seed)
+    ctx.check(lib().sabr_mc_price_noalloc(ctx.h, C.byref(m), C.byref(p), C.byref(mc), precision, _dp(price),
+                                          _dp(se)))
     return price, se
 
 
