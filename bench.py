@@ -31,30 +31,45 @@ sys.path.insert(0, ROOT)
 
 METRIC = "calibrations/s + p50/p99 latency; MC path-steps/s; asymptotic-formula evals/s"
 N_CHAINS, N_ITERS, CHAIN_LEN = 4096, 20000, 10
-# VALU issue peak of the chip in float lane-op slots: 256 CUs x 4 SIMDs x 32
-# lanes per clock x 2.4 GHz = 78.64 T/s (the published 157.3 TFLOP/s FP32
-# counts an FMA as two flops).  A double op takes 2 slots, a transcendental
-# (exp, log, sqrt, rcp, sin, cos) 4.
-PEAK_VALU_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
-# Algorithmic slots of one float Hagan point evaluation (z, s, x(z), z/x,
-# T-correction, vol, double residual and accumulation): 21 float ops, 3
-# transcendentals, 3 double ops = 21 + 12 + 6 = 39; and of one annealing
-# iteration outside the point loop (Philox4x32-10 with 20 32x32->64 multiplies
-# at quarter rate, the double proposal and the Metropolis test with its
-# double exp and division): ~200 slots.
-SLOTS_PER_PT_EVAL = 39
-# HBM bytes of one sa_kernel launch of this workload, from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each scaled by what the same
-# counter reads for a device copy of 256 MiB (FETCH_SIZE reads 131084 KiB of
-# the 262144 read, WRITE_SIZE exactly 262144): profiles/counters_sa_kernel_static_surface.md.
-# Almost all of it is the level-end exchange between workgroups (candidate
-# slots written and watched across the chip's L2 caches); the grids are read once.
-SA_FETCH_KIB, SA_WRITE_KIB = 1165956.0833, 144097.3125
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131084.1587, 1.0
-SA_TRAFFIC_BYTES = (SA_FETCH_KIB * FETCH_SCALE + SA_WRITE_KIB * WRITE_SCALE) * 1024
-# False once sa_kernel has changed since the counters above were taken (traffic then null)
-SA_COUNTERS_CURRENT = True
-SLOTS_SA_PER_ITER = 200
+# Roofline of the ALU-bound kernels: the published FP32 vector peak of the
+# chip, 157.3 TFLOP/s (256 CUs x 4 SIMDs x 32 FMA lanes per clock x 2 flops
+# x 2.4 GHz), against the algorithmic FP32 flops of each unit of work, counting
+# every FP32 add, multiply or FMA of the formula as an FMA (2 flops) and the
+# transcendentals (exp, log, sqrt, reciprocal, sin, cos) as none:
+#   static Hagan point evaluation       16 FP32 ops   = 32 flops (+ 3 transcendentals)
+#   dynamic point evaluation             6 FP32 FMAs  = 12 flops
+#   dynamic (chain, maturity) block     50 FP32 ops   = 100 flops (case I closed forms or series, + 2 exp)
+#   Monte Carlo chain-path-step          7 FP32 ops   = 14 flops (+ 1 exp)
+PEAK_FP32_TFLOPS = 157.3
+FLOP_STATIC_PT, FLOP_DYN_PT, FLOP_DYN_BLOCK, FLOP_MC_STEP = 32, 12, 100, 14
+TRANS_STATIC_PT = 3
+ROOT_PROFILES = os.path.join(ROOT, "profiles")
+
+
+def source_digest(files):
+    """sha256 prefix of the kernel sources a counter summary was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        h.update(open(os.path.join(ROOT, "paper_2407_20713_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+SA_SOURCES = ["sabr_dev.h", "sabr_formula.h", "sabr_sa.h", "kernels_formula.hip"]
+
+
+def counter_summary(name, sources):
+    """The machine-readable line of a committed counter summary under
+    profiles/ (`counters: {...}`), or None when the kernel sources have
+    changed since the counters were taken (its `sources` digest differs)."""
+    path = os.path.join(ROOT_PROFILES, name)
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("counters: "):
+            d = json.loads(line[len("counters: "):])
+            return d if d.get("sources") == source_digest(sources) else None
+    return None
 
 
 def build_requests(S, inputs, ctx, precision, polish=True):
@@ -99,26 +114,62 @@ def mc_path_steps(S, ctx, n_paths=1 << 24):
                 path_steps_per_s=n_paths * steps / (ms / 1e3))
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Host cores this process may use (at most 16, the CPU share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
 def cpu_baseline(reqs, gpu_results, sample_iters):
-    """The FP64 oracle on one host core: one fit of the same workload with
-    4096 chains and `sample_iters` iterations, scaled to full calibrations.
-    Also reports the largest vol difference between the GPU's float vols and
-    the oracle's double vols at the GPU's calibrated parameters."""
+    """The FP64 oracle on the host: one fit of the same workload with 4096
+    chains and `sample_iters` iterations on one core, scaled to full
+    calibrations; then every usable core (one thread each, the oracle runs in
+    C without the interpreter lock) on a fit of its own with half that many
+    iterations at once, for the aggregate rate."""
+    from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
-    req = reqs[5]
-    m = req.market
-    om = O.Market(m.T, m.fwd, m.offs, m.K, target=m.target)
-    p = req.problem
-    t = time.perf_counter()
-    O.calibrate(om, O.STATIC, p.lb, p.ub, p.beta, N_CHAINS, sample_iters, int(req.sa.seed),
-                cooling=req.sa.cooling, chain_len=CHAIN_LEN)
-    dt = time.perf_counter() - t
+
+    def one(k, iters):
+        req = reqs[k % len(reqs)]
+        m = req.market
+        om = O.Market(m.T, m.fwd, m.offs, m.K, target=m.target)
+        p = req.problem
+        t = time.perf_counter()
+        O.calibrate(om, O.STATIC, p.lb, p.ub, p.beta, N_CHAINS, iters, int(req.sa.seed),
+                    cooling=req.sa.cooling, chain_len=CHAIN_LEN)
+        return time.perf_counter() - t
+
+    dt = one(5, sample_iters)
     per_cal = dt * (N_ITERS / sample_iters)
-    return dict(value=1.0 / per_cal, unit="calibrations/s", cores=1, kind="oracle",
-                sample="1 of the 24 fits (25 strikes, T=%.3g), %d chains x %d of %d iterations, FP64, "
-                       "%.1f s measured, scaled by %d" % (m.T[0], N_CHAINS, sample_iters, N_ITERS, dt,
-                                                           N_ITERS // sample_iters),
-                ns_per_point_eval=dt / (N_CHAINS * sample_iters * m.n_obs) * 1e9)
+    n_thr = host_threads()
+    it_all = max(sample_iters // 2, 10)
+    with ThreadPoolExecutor(n_thr) as ex:
+        t = time.perf_counter()
+        times = list(ex.map(lambda k: one(k, it_all), range(n_thr)))
+        wall = time.perf_counter() - t
+    agg = n_thr / (wall * (N_ITERS / it_all))
+    m = reqs[5].market
+    return dict(value=agg, unit="calibrations/s", cores=n_thr, kind="oracle", cpu_model=cpu_model(),
+                sample="%d threads at once, each one of the 24 fits (25 strikes) with %d chains x %d of %d "
+                       "iterations, FP64, %.1f s wall (%.1f s of CPU), scaled by %d" % (
+                           n_thr, N_CHAINS, it_all, N_ITERS, wall, sum(times), N_ITERS // it_all),
+                single_core={"value": 1.0 / per_cal, "unit": "calibrations/s", "cores": 1,
+                             "sample": "1 fit (T=%.3g), %d chains x %d of %d iterations, %.1f s, scaled by %d" % (
+                                 m.T[0], N_CHAINS, sample_iters, N_ITERS, dt, N_ITERS // sample_iters),
+                             "ns_per_point_eval": dt / (N_CHAINS * sample_iters * m.n_obs) * 1e9})
 
 
 def fp32_vs_oracle(S, ctx, reqs, results):
@@ -136,35 +187,66 @@ def fp32_vs_oracle(S, ctx, reqs, results):
 
 
 # --- other workloads (not the default line) ------------------------------------
+def roofline(flops, kernel_s, kernel, launches, counters=None):
+    d = {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+         "frac": flops / kernel_s / 1e12 / PEAK_FP32_TFLOPS, "traffic": None, "kernel": kernel,
+         "avg_kernel_ms": kernel_s * 1e3, "launches": launches}
+    if counters:
+        d["traffic"] = counters.get("traffic_bytes_per_launch")
+        d["valu_insts_per_simd_cycle"] = counters.get("valu_insts_per_simd_cycle")
+        d["valu_busy_rocprof"] = counters.get("valu_busy_rocprof")
+        d["counters_from"] = counters.get("file")
+    return d
+
+
 def bench_mc_calibration(S, inputs, ctx, args):
     """Monte Carlo objective calibration: 8 quarterly maturities x 15 strikes,
-    static SABR (beta 0.7), targets from a 2^22-path FP64 run at the true
-    parameters, 1024 chains x `iters` iterations x 65536 common paths,
-    250 steps per year, relative squared price errors."""
+    static SABR (beta 0.7), 1024 chains x `iters` iterations x 65536 common
+    paths, 250 steps per year, relative squared price errors; targets from a
+    2^22-path FP64 run at the true parameters (Monte Carlo noise bounds the
+    recovery), and, as the self-consistent variant, targets priced on the
+    same 65536 common paths at the true parameters (the truth is then an
+    exact minimum)."""
     g = inputs.mc_grid()
     xt = g.meta["x_true"]
     lb, ub = inputs.box(inputs.STATIC)
+    iters = args.mc_iters
     tgt, _ = S.sabr_mc_price(ctx, S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7, x0=xt), 1 << 22, 250,
                              g.meta["target_seed"], precision=S.SABR_FP64)
-    iters = args.mc_iters
-    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
-                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=1024,
-                    n_iters=iters, cooling=0.99 ** (1000.0 / 500), seed=0x5AB30001, n_paths=65536,
-                    steps_per_year=250, mc_seed=g.meta["mc_seed"])
-    S.sabr_ctx_enable_timing(ctx, True)
-    S.sabr_ctx_timing(ctx, reset=True)
-    t = time.perf_counter()
-    res = S.sabr_calibrate(ctx, req)
-    wall = time.perf_counter() - t
-    ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
+    _, same = S.sabr_objective_batch(ctx, S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7), xt[None, :],
+                                     kind=S.SABR_OBJ_MC, precision=S.SABR_FP32, n_paths=65536, steps_per_year=250,
+                                     mc_seed=g.meta["mc_seed"], want_model=True)
+
+    def run(target):
+        req = S.Request(S.Market.from_grid(g, target=target), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                        kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=1024,
+                        n_iters=iters, cooling=0.99 ** (1000.0 / 500), seed=0x5AB30001, n_paths=65536,
+                        steps_per_year=250, mc_seed=g.meta["mc_seed"])
+        S.sabr_ctx_enable_timing(ctx, True)
+        S.sabr_ctx_timing(ctx, reset=True)
+        t = time.perf_counter()
+        res = S.sabr_calibrate(ctx, req)
+        wall = time.perf_counter() - t
+        ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
+        return res, wall, ms, n, name
+
+    res, wall, ms, n, name = run(tgt)
+    res_same, wall2, _, _, _ = run(same[0])
     m_max = 500
     cps = 1024 * 65536 * m_max * iters
+    k_s = ms / 1e3 / max(n, 1)
     return {"metric": "MC path-steps/s", "value": cps / wall, "unit": "chain-path-steps/s",
-            "kernel": name, "kernel_chain_path_steps_per_s": cps / (n and ms / 1e3 or 1),
-            "avg_kernel_ms": ms / max(n, 1), "launches": n, "wall_s": wall,
+            "kernel_chain_path_steps_per_s": cps / (ms / 1e3) if ms else None, "wall_s": wall,
+            "calibrations_per_s": 1.0 / wall,
             "config": {"workload": "MC-objective calibration, 8 x 15 calls, 1024 chains x %d iterations x 65536 "
                                    "paths x 500 steps, FP32 paths" % iters},
-            "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"]}
+            "roofline": roofline(1024 * 65536 * m_max * FLOP_MC_STEP, k_s, name, n,
+                                 counter_summary("counters_mc_crn_kernel_mc_calibration.md",
+                                                 ["sabr_dev.h", "sabr_mc.h", "kernels_mc.hip"])),
+            "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"],
+            "self_consistent": {"param_error_vs_truth": float(np.max(np.abs(res_same["x"] - xt))),
+                                "f": res_same["f"], "wall_s": wall2,
+                                "targets": "FP32 prices on the same 65536 common paths at the truth"}}
 
 
 def bench_dynamic(S, inputs, ctx, args):
@@ -182,14 +264,21 @@ def bench_dynamic(S, inputs, ctx, args):
     S.sabr_ctx_enable_timing(ctx, True)
     S.sabr_calibrate(ctx, req)
     S.sabr_ctx_timing(ctx, reset=True)
+    reps = 3
     t = time.perf_counter()
-    res = S.sabr_calibrate(ctx, req)
-    wall = time.perf_counter() - t
+    for _ in range(reps):
+        res = S.sabr_calibrate(ctx, req)
+    wall = (time.perf_counter() - t) / reps
     ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
+    k_s = ms / 1e3 / max(n, 1)
     pts = 8192 * iters * g.n_obs
+    flops = pts * FLOP_DYN_PT + 8192 * iters * g.n_mat * FLOP_DYN_BLOCK
     return {"metric": "asymptotic-formula evals/s", "value": pts / wall, "unit": "point-evals/s",
-            "calibrations_per_s": 1.0 / wall, "kernel": name, "avg_kernel_ms": ms / max(n, 1), "wall_s": wall,
-            "config": {"workload": "dynamic SABR case I, 20 x 20 joint fit, 8192 chains x %d iterations" % iters},
+            "calibrations_per_s": 1.0 / wall, "wall_s": wall,
+            "config": {"workload": "dynamic SABR case I, 20 x 20 joint fit, 8192 chains x %d iterations, FP32 "
+                                   "bulk, FP64 polish" % iters},
+            "roofline": roofline(flops, k_s, name, n,
+                                 counter_summary("counters_sa_kernel_dynamic_case1.md", SA_SOURCES)),
             "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"]}
 
 
@@ -246,38 +335,52 @@ def serve(S, ctx, trace, reqs, rate_scale, max_slots, quantum):
 
 
 def bench_serving(S, inputs, ctx, args):
+    """Config 5: capacity (every request submitted at once), then the trace's
+    Poisson arrivals at a rate the server sustains (served rate within 5 % of
+    the offered rate, found by trying 0.5 and then 0.35 of the capacity), and
+    the first `serve_baseline` requests of the same arrivals served one
+    sabr_calibrate call per request, first come first served."""
     n = args.serve_requests
     trace, reqs = serving_requests(S, inputs, ctx, n, 1.0, 0x5AB5, args.serve_paths)
-    # capacity: every request submitted at once
     lat_b, span_b, st_b = serve(S, ctx, trace, reqs, 0.0, args.serve_slots, args.serve_quantum)
     capacity = n / span_b
-    # Poisson arrivals at 0.8 x capacity (the trace is drawn at rate 1; scale its times)
-    lat_s, span_s, st_s = serve(S, ctx, trace, reqs, 1.0 / (0.8 * capacity), args.serve_slots, args.serve_quantum)
-    # baseline: the same trace, one sabr_calibrate call per request, FIFO, same arrival times
+    tried = []
+    for frac in (0.5, 0.35):
+        rate = frac * capacity
+        lat_s, span_s, st_s = serve(S, ctx, trace, reqs, 1.0 / rate, args.serve_slots, args.serve_quantum)
+        offered = n / (trace[-1].arrival_s / rate)
+        served = n / span_s
+        tried.append({"fraction_of_capacity": frac, "offered_per_s": offered, "served_per_s": served,
+                      "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
+                      "p99_ms": float(np.percentile(lat_s, 99) * 1e3)})
+        if served >= 0.95 * offered:
+            break
+    nb = min(args.serve_baseline, n)
     t0 = time.perf_counter()
     lat_1 = []
-    for tr, r in zip(trace, reqs):
-        arr = tr.arrival_s / (0.8 * capacity)
+    for tr, r in zip(trace[:nb], reqs[:nb]):
+        arr = tr.arrival_s / rate
         now = time.perf_counter() - t0
         if now < arr:
             time.sleep(arr - now)
         S.sabr_calibrate(ctx, r)
         lat_1.append(time.perf_counter() - t0 - arr)
-        if len(lat_1) % 200 == 0:
-            print("one-per-launch %d / %d" % (len(lat_1), len(reqs)), file=sys.stderr, flush=True)
+        if len(lat_1) % 500 == 0:
+            print("one-per-launch %d / %d" % (len(lat_1), nb), file=sys.stderr, flush=True)
     span_1 = time.perf_counter() - t0
     lat_1 = np.array(lat_1)
     kinds = {k: sum(1 for t in trace if t.kind == k) for k in ("static", "dynamic", "mc")}
-    return {"metric": "calibrations/s + p50/p99 latency", "value": n / span_s, "unit": "calibrations/s",
-            "config": {"workload": "serving trace: %d requests, Poisson arrivals at 0.8 x measured capacity, "
-                                   "1-20 maturities x 5-41 strikes, mix %s, Monte Carlo %d paths" % (
-                                       n, kinds, args.serve_paths),
+    last = tried[-1]
+    return {"metric": "calibrations/s + p50/p99 latency", "value": last["served_per_s"], "unit": "calibrations/s",
+            "config": {"workload": "serving trace: %d requests, Poisson arrivals, 1-20 maturities x 5-41 strikes, "
+                                   "mix %s, Monte Carlo %d paths" % (n, kinds, args.serve_paths),
                        "slots": args.serve_slots, "quantum_levels": args.serve_quantum},
             "capacity_calibrations_per_s": capacity,
-            "served": {"calibrations_per_s": n / span_s, "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
-                       "p99_ms": float(np.percentile(lat_s, 99) * 1e3), "peak_active": st_s["peak_active"],
-                       "peak_bytes": st_s["peak_bytes"], "quanta": st_s["quanta"]},
-            "one_request_per_launch": {"calibrations_per_s": n / span_1,
+            "sustained": dict(last, sustained=last["served_per_s"] >= 0.95 * last["offered_per_s"],
+                              peak_active=st_s["peak_active"], peak_bytes=st_s["peak_bytes"], quanta=st_s["quanta"]),
+            "rates_tried": tried,
+            "one_request_per_launch": {"requests": nb, "offered_per_s": last["offered_per_s"],
+                                       "calibrations_per_s": nb / span_1,
                                        "p50_ms": float(np.percentile(lat_1, 50) * 1e3),
                                        "p99_ms": float(np.percentile(lat_1, 99) * 1e3)}}
 
@@ -313,21 +416,26 @@ def main():
     ap.add_argument("--serve-paths", type=int, default=16384)
     ap.add_argument("--serve-slots", type=int, default=1024)
     ap.add_argument("--serve-quantum", type=int, default=20)
+    ap.add_argument("--serve-baseline", type=int, default=2000)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-iters", type=int, default=2000)
     ap.add_argument("--no-mc", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="the static surface line only (no other configs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the calibration path is built and measured on a single "
               "MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import torch
+    # No torch here (the copy reference aside): every library call below
+    # returns only after the library's stream has finished, and without
+    # torch the library binds to the HIP runtime under /opt/rocm, the one a
+    # profiler attached to this process instruments.
     from paper_2407_20713_amd import inputs, sabr as S
 
-    S.lib()
+    S.lib(bind_torch_runtime=args.workload == "copy")
     ctx = S.sabr_ctx_create(0)
     if args.workload != "surface":
         fn = {"mc_calibration": bench_mc_calibration, "dynamic": bench_dynamic, "serving": bench_serving,
@@ -352,13 +460,11 @@ def main():
     # charged to a step
     gc.collect()
     gc.disable()
-    torch.cuda.synchronize()
     t_all = time.perf_counter()
     for _ in range(args.steps):
         t = time.perf_counter()
-        S.sabr_batch_run(batch, raw=True)
+        S.sabr_batch_run(batch, raw=True)      # returns with the device idle
         lat.append(time.perf_counter() - t)
-    torch.cuda.synchronize()
     total = time.perf_counter() - t_all
     gc.enable()
     kernel_ms, launches, kname = S.sabr_ctx_timing(ctx, reset=True)
@@ -366,23 +472,22 @@ def main():
     # the same calibrations from host arrays (validation, packing and the
     # host-to-device copies included in every call); reported beside the value
     n_host = min(args.steps, 3)
-    torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(n_host):
         host_res = S.sabr_calibrate_many(ctx, reqs)
-    torch.cuda.synchronize()
     host_s = (time.perf_counter() - t) / max(n_host, 1)
     same = all(np.array_equal(a["x"], b["x"]) and a["f"] == b["f"] for a, b in zip(results, host_res))
     S.sabr_batch_destroy(batch)
 
     n_cal = len(reqs)
     pts = sum(r.market.n_obs for r in reqs)
-    pt_evals = N_CHAINS * N_ITERS * pts            # per step
+    pt_evals = N_CHAINS * N_ITERS * pts            # per step (one sa_kernel launch)
     avg_kernel_s = kernel_ms / 1e3 / max(launches, 1)
-    slots = pt_evals * SLOTS_PER_PT_EVAL + n_cal * N_CHAINS * N_ITERS * SLOTS_SA_PER_ITER
-    achieved = slots / avg_kernel_s / 1e12
     param_err = max(float(np.max(np.abs(r["x"] - x))) for r, x in zip(results, truths))
     lat_ms = np.array(lat) * 1e3
+    rl = roofline(pt_evals * FLOP_STATIC_PT, avg_kernel_s, kname, launches,
+                  counter_summary("counters_sa_kernel_static_surface.md", SA_SOURCES))
+    rl["transcendentals_per_s"] = pt_evals * TRANS_STATIC_PT / avg_kernel_s
     out = {
         "metric": METRIC,
         "value": n_cal * args.steps / total,
@@ -407,15 +512,20 @@ def main():
         "host_inputs": {"calibrations_per_s": n_cal / host_s, "ms_per_step": host_s * 1e3, "steps": n_host,
                         "identical_results": same},
         "max_param_error_vs_truth": param_err,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": SA_TRAFFIC_BYTES if SA_COUNTERS_CURRENT else None,
-                     "kernel": kname, "avg_kernel_ms": avg_kernel_s * 1e3, "launches": launches},
+        "roofline": rl,
     }
     if not args.no_mc:
         out["mc_path_steps"] = mc_path_steps(S, ctx)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(reqs, results, args.cpu_sample_iters)
         out["max_vol_error_fp32_vs_oracle"] = fp32_vs_oracle(S, ctx, reqs, results)
+    if not args.no_extra:
+        print("static surface done; other configs follow", file=sys.stderr, flush=True)
+        out["configs"] = {}
+        for name, fn in (("dynamic", bench_dynamic), ("mc_calibration", bench_mc_calibration),
+                         ("serving", bench_serving)):
+            out["configs"][name] = fn(S, inputs, ctx, args)
+            print("%s done" % name, file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(out))
 

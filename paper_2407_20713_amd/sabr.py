@@ -80,18 +80,23 @@ class SabrError(RuntimeError):
 _lib = None
 
 
-def lib():
-    """Load libsabr_hip.so; raise if it has not been built."""
+def lib(bind_torch_runtime=True):
+    """Load libsabr_hip.so; raise if it has not been built.
+
+    PyTorch ships its own HIP runtime under the same soname
+    (libamdhip64.so.7).  With bind_torch_runtime (the default) torch is
+    imported first, so that this library binds to that runtime and one
+    runtime serves torch's memory and streams and this library's kernels
+    (the other order leaves torch without a GPU).  Without it the library
+    binds to the system runtime, and torch must not be used with the GPU in
+    this process."""
     global _lib
     if _lib is None:
-        # PyTorch ships its own HIP runtime under the same soname
-        # (libamdhip64.so.7).  Loading torch first makes this library bind to
-        # that runtime, so one runtime serves torch's memory and streams and
-        # this library's kernels; the other order leaves torch without a GPU.
-        try:
-            import torch  # noqa: F401
-        except ImportError:
-            pass
+        if bind_torch_runtime:
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
         if not os.path.exists(LIB_PATH):
             raise ImportError("libsabr_hip.so is not built (run __graft_entry__.build() or "
                               "python -m paper_2407_20713_amd.build)")
