@@ -278,7 +278,7 @@ def bench_dynamic(S, inputs, ctx, args):
             "config": {"workload": "dynamic SABR case I, 20 x 20 joint fit, 8192 chains x %d iterations, FP32 "
                                    "bulk, FP64 polish" % iters},
             "roofline": roofline(flops, k_s, name, n,
-                                 counter_summary("counters_sa_kernel_dynamic_case1.md", SA_SOURCES)),
+                                 counter_summary("sa_kernel_dynamic_case1.md", SA_SOURCES)),
             "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"]}
 
 
