@@ -215,11 +215,14 @@ template <> struct M<double> {
 template <typename R> struct CaseI;
 template <> struct CaseI<double> {
     static constexpr double kSwitch = 1.0;
-    static constexpr int kTerms = 22;
+    static constexpr int kN1 = 22, kN2 = 22, kE1 = 22, kE2 = 22;
 };
+// Float: below the switch point 2 the truncation after 12 / 13 / 13 / 16
+// terms stays below the float rounding of the sums (largest relative error
+// 2.6e-7 / 2.8e-7 / 3.2e-7 / 9.7e-7 over [0, 2], the same as with more terms).
 template <> struct CaseI<float> {
     static constexpr double kSwitch = 2.0;
-    static constexpr int kTerms = 18;
+    static constexpr int kN1 = 12, kN2 = 13, kE1 = 13, kE2 = 16;
 };
 
 __host__ __device__ constexpr double factorial(int n) {
@@ -257,11 +260,10 @@ __device__ __forceinline__ R series_even_odd(R z, C c) {
 
 template <typename R>
 __device__ __forceinline__ void case1_normalised(R y, R x, R &n1, R &n2, R &e1, R &e2) {
-    constexpr int NT = CaseI<R>::kTerms;
     if (fabs((double)y) < CaseI<R>::kSwitch) {
         // c_k = 6/(k+3)! and 6(k+1)/(k+3)!
-        n1 = series_even_odd<R, NT>(-y, [](int k) { return 6.0 / factorial(k + 3); });
-        n2 = series_even_odd<R, NT>(-y, [](int k) { return 6.0 * (k + 1) / factorial(k + 3); });
+        n1 = series_even_odd<R, CaseI<R>::kN1>(-y, [](int k) { return 6.0 / factorial(k + 3); });
+        n2 = series_even_odd<R, CaseI<R>::kN2>(-y, [](int k) { return 6.0 * (k + 1) / factorial(k + 3); });
     } else {
         const R ey = M<R>::ex(-y);
         const R c = (R)6 * M<R>::rcp(y * y * y);
@@ -270,8 +272,8 @@ __device__ __forceinline__ void case1_normalised(R y, R x, R &n1, R &n2, R &e1, 
     }
     if (fabs((double)x) < CaseI<R>::kSwitch) {
         // c_k = 2/(k+2)! and 3 (2^(k+4) - 8)/(k+4)!
-        e1 = series_even_odd<R, NT>(-x, [](int k) { return 2.0 / factorial(k + 2); });
-        e2 = series_even_odd<R, NT>(-x, [](int k) { return 3.0 * (pow2(k + 4) - 8.0) / factorial(k + 4); });
+        e1 = series_even_odd<R, CaseI<R>::kE1>(-x, [](int k) { return 2.0 / factorial(k + 2); });
+        e2 = series_even_odd<R, CaseI<R>::kE2>(-x, [](int k) { return 3.0 * (pow2(k + 4) - 8.0) / factorial(k + 4); });
     } else {
         const R ex = M<R>::ex(-x);
         const R ix2 = M<R>::rcp(x * x);

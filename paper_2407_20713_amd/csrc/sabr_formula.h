@@ -122,9 +122,16 @@ __device__ __forceinline__ Quad<R> expansion_block(R F1, R T, R al, R beta, R rh
 template <typename R>
 __device__ __forceinline__ Quad<R> dynamic_block(R F1, R T, R al, R beta, R n1sq, R n2sq, R e1, R e2sq) {
     const R omb = (R)1 - beta;
-    const R w = F1 / al;
     Quad<R> q;
-    q.inv_w = al / F1;
+    R w;
+    if constexpr (sizeof(R) == 4) {
+        // float bulk: hardware reciprocals (1 ulp) instead of two divisions
+        w = F1 * M<R>::rcp(al);
+        q.inv_w = al * M<R>::rcp(F1);
+    } else {
+        w = F1 / al;
+        q.inv_w = al / F1;
+    }
     q.A1 = (beta - (R)1) * (R)0.5 + e1 * w * (R)0.5;
     q.A2 = omb * omb * (R)(1.0 / 12.0) + (omb - e1 * w) * (R)0.25
          + ((R)4 * n1sq + (R)3 * (e2sq - (R)3 * e1 * e1)) * (R)(1.0 / 24.0) * w * w;
@@ -417,6 +424,12 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
     // squares summed in double (so the sum hardly depends on how the points
     // are split over lanes); double: one sum in point order
     constexpr bool kTwo = sizeof(R) == 4;
+    // float without model output: the smallest vol tracked on the bit patterns
+    // as signed integers (every float with its sign bit set, and +0, compare
+    // at or below 0; +inf and NaN make the sum infinite or NaN), one integer
+    // minimum per point instead of two tests
+    constexpr bool kIntMin = kTwo && !WRITE;
+    int cmin = 0x7fffffff;
     double acc1 = 0.0, acc2 = 0.0;
     for (int i = rsub; i < n_mat; i += RS) {
         const Row<R> rw = rows[i];
@@ -425,7 +438,10 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         for (; kTwo && j + PS < rw.p1; j += 2 * PS) {
             const Pt<R> pa = pts[j], pb = pts[j + PS];
             const R sa = ev.point(pa), sb = ev.point(pb);
-            bad |= !vol_ok(sa) || !vol_ok(sb);
+            if constexpr (kIntMin)
+                cmin = min(min(cmin, __builtin_bit_cast(int, (float)sa)), __builtin_bit_cast(int, (float)sb));
+            else
+                bad |= !vol_ok(sa) || !vol_ok(sb);
             const double ea = (double)fma(-sa, pa.sw, pa.tsw), eb = (double)fma(-sb, pb.sw, pb.tsw);
             acc1 = fma(ea, ea, acc1);
             acc2 = fma(eb, eb, acc2);
@@ -437,13 +453,17 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         for (; j < rw.p1; j += PS) {
             const Pt<R> p = pts[j];
             const R sig = ev.point(p);
-            bad |= !vol_ok(sig);
+            if constexpr (kIntMin)
+                cmin = min(cmin, __builtin_bit_cast(int, (float)sig));
+            else
+                bad |= !vol_ok(sig);
             const double e = (double)fma(-sig, p.sw, p.tsw);
             acc1 = fma(e, e, acc1);
             if (WRITE) out[j] = (double)sig;
         }
     }
     if constexpr (kTwo) acc1 = acc1 + acc2;
+    if constexpr (kIntMin) return (cmin > 0 && acc1 < __builtin_inf()) ? acc1 : __builtin_inf();
     return bad ? __builtin_inf() : acc1;
 }
 
