@@ -4,7 +4,7 @@ same seeded inputs.
 Tolerances (stated once, used below):
   formula objective, FP64 mode : |df| <= 1e-12 f + 1e-14 sqrt(f S), S = sum w target^2
                                  (rounding of the model vols bounds |df| by ~eps sqrt(f S));
-  model vols, FP64 mode        : 1e-13 relative (case II quadrature: 1e-10);
+  model vols, FP64 mode        : 1e-13 relative + 1e-15 absolute (case II quadrature: 1e-10 relative);
   model vols, FP32 mode        : 2e-5 absolute vol;
   Monte Carlo prices, FP32     : 5e-5 relative on identical normals (plus 1e-7 absolute
                                  for prices of deep out-of-the-money strikes near 0);
@@ -792,3 +792,63 @@ def test_surface_full_size_sampled(S, ctx, oracle):
         assert abs(r["f"] - ref_f) <= 1e-12 * ref_f + 1e-14 * math.sqrt(ref_f * np.sum(m.target ** 2)) + 1e-28
         assert r["f_before_polish"] >= r["f"] - 1e-6 * r["f_before_polish"] - 1e-20
         np.testing.assert_allclose(r["x"], truths[k], rtol=0, atol=1e-6)
+
+
+def test_dynamic_full_size_sampled(S, ctx, oracle):
+    """The dynamic workload in the benchmark's launch configuration (case I,
+    20 x 20 joint fit, 8192 chains x 50000 iterations, float annealing with
+    16 lanes per chain, FP64 polish): the reported objective equals the
+    oracle's FP64 objective at the reported parameters and the noise-free
+    truth is recovered."""
+    g = inputs.dynamic_surface()
+    xt = g.meta["x_true"]
+    m = omkt(oracle, g)
+    tgt = oracle.model_vols(m, oracle.DYN_I, xt, 0.7)
+    m.target = tgt
+    lb, ub = inputs.box(inputs.DYN_I)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_DYN_I, 0.7, lb, ub),
+                    precision=S.SABR_FP32, n_chains=8192, n_iters=50000, cooling=0.99 ** (1000.0 / 50000),
+                    seed=0x5AB40001, polish=True)
+    r = S.sabr_calibrate(ctx, req)
+    ref_f = oracle.objective_formula(m, oracle.DYN_I, r["x"], 0.7)
+    say("dynamic full size", r["x"], r["f"], "oracle f", ref_f, "before polish", r["f_before_polish"])
+    assert r["status"] == 0
+    assert abs(r["f"] - ref_f) <= 1e-12 * ref_f + 1e-14 * math.sqrt(ref_f * np.sum(tgt ** 2)) + 1e-28
+    np.testing.assert_allclose(r["x"], xt, rtol=0, atol=1e-6)
+
+
+def test_mc_calibration_full_size_self_consistent(S, ctx, oracle):
+    """The Monte Carlo workload in the benchmark's launch configuration (8 x 15
+    calls, 1024 chains x 500 iterations x 65536 common paths x 250 steps per
+    year) with targets priced on the same paths at the truth: the truth is
+    recovered to 1e-3, and the reported objective equals the oracle's Monte
+    Carlo objective on the same normals at the reported parameters, within
+    what prices at 5e-5 relative allow."""
+    g = inputs.mc_grid()
+    xt = g.meta["x_true"]
+    lb, ub = inputs.box(inputs.STATIC)
+    mk = S.Market.from_grid(g)
+    _, tgt = S.sabr_objective_batch(ctx, mk, S.Problem(S.SABR_STATIC, 0.7), xt[None, :], kind=S.SABR_OBJ_MC,
+                                    precision=S.SABR_FP32, n_paths=65536, steps_per_year=250,
+                                    mc_seed=g.meta["mc_seed"], want_model=True)
+    req = S.Request(S.Market.from_grid(g, target=tgt[0]), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=1024,
+                    n_iters=500, cooling=0.99 ** 2, seed=0x5AB30001, n_paths=65536, steps_per_year=250,
+                    mc_seed=g.meta["mc_seed"])
+    r = S.sabr_calibrate(ctx, req)
+    say("mc full size", r["x"], r["f"])
+    assert r["status"] == 0
+    np.testing.assert_allclose(r["x"], xt, atol=1e-3)
+    # the oracle on all 65536 paths (each FP64 evaluation takes a few seconds)
+    m = omkt(oracle, g, target=tgt[0])
+    ref_f = oracle.objective_mc(m, oracle.STATIC, r["x"], 0.7, 65536, 250, g.meta["mc_seed"])
+    ref_p, _ = oracle.mc_prices(m, oracle.STATIC, r["x"], 0.7, 65536, 250, g.meta["mc_seed"])
+    _, got_p = S.sabr_objective_batch(ctx, mk, S.Problem(S.SABR_STATIC, 0.7), r["x"][None, :], kind=S.SABR_OBJ_MC,
+                                      precision=S.SABR_FP32, n_paths=65536, steps_per_year=250,
+                                      mc_seed=g.meta["mc_seed"], want_model=True)
+    np.testing.assert_allclose(got_p[0], ref_p, rtol=5e-5, atol=1e-7)
+    # relative price residuals e_j agree to delta = 5e-5, so |df| <= sum (2 |e_j| delta + delta^2)
+    delta, n = 5e-5, g.n_obs
+    tol = 2.0 * math.sqrt(ref_f * n) * delta + n * delta ** 2 + 1e-3 * ref_f
+    say("oracle f", ref_f, "tol", tol)
+    assert abs(r["f"] - ref_f) <= tol
