@@ -306,8 +306,9 @@ int sabr_mc_cliquet(sabr_ctx *ctx, const sabr_problem *problem, double f0, doubl
  * kind) until a slot of its kind is free and its device footprint (grid, schedule, chain state, Monte Carlo
  * partials) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each formula
  * quantum replays a captured HIP graph that normalises new grids, advances
- * every formula slot by quantum_levels temperature levels and copies the
- * slot states back; beside it, on a second stream, a second captured graph
+ * every formula slot by up to quantum_levels temperature levels (fewer for
+ * slots whose grids make a level costly, so that one large request does not
+ * stretch every quantum) and copies the slot states back; beside it, on a second stream, a second captured graph
  * advances every Monte Carlo slot by one iteration and is relaunched as soon
  * as it finishes.  Requests admitted while others run join at the next
  * launch.  Slots 0..max_slots/8-1 take Monte Carlo requests, the others

@@ -102,7 +102,7 @@ __device__ void sa_slot_body(SlotDev &s, int Q, unsigned char *smem) {
         nacc = s.nacc[c];
         T0 = s.T0;
     }
-    const int lev1 = min(lev0 + Q, rq.n_levels);
+    const int lev1 = min(lev0 + (s.q_levels > 0 ? min(Q, s.q_levels) : Q), rq.n_levels);
     for (int lev = lev0; lev < lev1; ++lev) {
         const double h = s.sched_h[lev];
         const double Tk = T0 * s.sched_g[lev];

@@ -24,7 +24,8 @@ __host__ __device__ inline int mc_slot_class(int n_obs) { return n_obs <= mc_cla
 // request's own region of the server's arena; grid offsets are slot-local.
 struct SlotDev {
     ReqDesc rq;              // n_wg = 1; pt_off = mat_off = 0
-    int32_t state, kind, level, pad0;
+    int32_t state, kind, level;
+    int32_t q_levels;        // levels this slot advances per quantum (at most the server's Q)
     // grid: raw inputs and normalised values (slot-local CSR)
     const double *K;         // [n_pts]
     double *lfk, *lkf, *P1, *Z, *Q1, *Q2, *target, *sw;   // [n_pts]

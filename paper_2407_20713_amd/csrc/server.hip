@@ -215,6 +215,21 @@ int stage_copy(sabr_server *s, void *dst, const void *src, size_t bytes) {
     return hipMemcpyAsync(dst, h, bytes, hipMemcpyHostToDevice, s->stream) == hipSuccess ? SABR_OK : SABR_E_DEVICE;
 }
 
+// Temperature levels a formula slot advances per quantum.  A quantum lasts as
+// long as its slowest slot, so each slot takes as many levels as keep its work
+// within four full quanta of the largest static slot (41 strikes, two lanes
+// per chain), at least one and at most Q.  Work per iteration and lane, in
+// point evaluations: static ceil(n_pts / 2) + 8 (proposal, random words,
+// Metropolis test), dynamic n_pts + 15 n_mat (the row blocks) + 10.  A
+// request's result does not depend on how its levels are cut into quanta.
+int slot_quantum_levels(int Q, int kind, int n_pts, int n_mat) {
+    if (kind == KIND_MC) return Q;
+    const double ref = 4.0 * Q * (21 + 8);
+    const double c = kind == KIND_STATIC ? (n_pts + 1) / 2 + 8 : n_pts + 15.0 * n_mat + 10;
+    const int q = (int)(ref / c);
+    return q < 1 ? 1 : (q > Q ? Q : q);
+}
+
 // Build the device slot of request `o` in slot `si` (arena block at `base`).
 int upload_slot(sabr_server *s, int si, const Owned &o, size_t base) {
     const sabr_request &q = o.req;
@@ -254,6 +269,7 @@ int upload_slot(sabr_server *s, int si, const Owned &o, size_t base) {
     d.kind = slot_kind(q);
     d.state = SLOT_NEW;
     d.level = 0;
+    d.q_levels = slot_quantum_levels(s->Q, d.kind, n_pts, n_mat);
     d.iter = -1;
     // descriptor
     ReqDesc &rq = d.rq;
