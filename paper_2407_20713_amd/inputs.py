@@ -2,8 +2,10 @@
 noise and request traces.
 
 This module holds no SABR arithmetic (no implied-vol formula, no path
-scheme): it only lays out strikes and maturities and draws random numbers
-with numpy's PCG64.  Model values at the drawn parameters are computed by
+scheme): it only lays out strikes and maturities and draws random numbers:
+the workloads' true parameters and vol noise from Philox4x32-10 streams
+(counter (calibration id, redraw, 0, 4) and (point, 0, 0, 3)), the serving
+trace from numpy's PCG64.  Model values at the drawn parameters are computed by
 whoever uses the grid (the oracle in the tests, the HIP library in the
 benchmark), so both sides see the same inputs.
 
@@ -17,6 +19,44 @@ from dataclasses import dataclass, field
 import numpy as np
 
 STATIC, DYN_I, DYN_II = 0, 1, 2
+TAG_NOISE, TAG_TRUE = 3, 4
+
+
+# --- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11), for the workloads' draws ---
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of counters ctr[..., 4] under key (k0, k1); uint32 words [..., 4]."""
+    c = np.asarray(ctr, dtype=np.uint64).reshape(-1, 4).copy()
+    mask = np.uint64(0xFFFFFFFF)
+    k0, k1 = np.uint64(key[0]) & mask, np.uint64(key[1]) & mask
+    m0, m1 = np.uint64(0xD2511F53), np.uint64(0xCD9E8D57)
+    for _ in range(10):
+        p0 = m0 * c[:, 0]
+        p1 = m1 * c[:, 2]
+        c = np.stack([(p1 >> np.uint64(32)) ^ c[:, 1] ^ k0, p1 & mask,
+                      (p0 >> np.uint64(32)) ^ c[:, 3] ^ k1, p0 & mask], axis=1)
+        k0 = (k0 + np.uint64(0x9E3779B9)) & mask
+        k1 = (k1 + np.uint64(0xBB67AE85)) & mask
+    return c.astype(np.uint32).reshape(np.shape(ctr))
+
+
+def _key(seed):
+    return (int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF)
+
+
+class PhiloxStream:
+    """Uniforms (w + 1/2) 2^-32 in (0, 1) from Philox4x32-10 under key `seed`:
+    the d-th call of random(n) reads the words of counters (stream, d, b, tag),
+    b = 0, 1, ... (a redraw takes the next d)."""
+
+    def __init__(self, seed, stream, tag):
+        self.key, self.stream, self.tag, self.draw = _key(seed), int(stream), int(tag), 0
+
+    def random(self, n):
+        nb = (n + 3) // 4
+        ctr = [(self.stream, self.draw, b, self.tag) for b in range(nb)]
+        w = philox4x32_10(np.array(ctr, dtype=np.uint64), self.key).ravel()[:n]
+        self.draw += 1
+        return (w.astype(np.float64) + 0.5) * 2.0 ** -32
 
 
 @dataclass
@@ -76,7 +116,16 @@ def draw_params(rng, lb, ub):
 
 
 def vol_noise(rng, n, sd=1e-4):
-    """Gaussian noise of standard deviation sd (absolute vol)."""
+    """Gaussian noise of standard deviation sd (absolute vol).  rng is a
+    numpy Generator, or an integer key: then point j takes the first two
+    words of Philox4x32-10 at counter (j, 0, 0, 3) as uniforms u1, u2 and
+    the Box-Muller normal sqrt(-2 ln u1) cos(2 pi u2)."""
+    if isinstance(rng, (int, np.integer)):
+        ctr = np.array([(j, 0, 0, TAG_NOISE) for j in range(n)], dtype=np.uint64).reshape(-1, 4)
+        w = philox4x32_10(ctr, _key(rng)).astype(np.float64) if n else np.zeros((0, 4))
+        u1 = (w[:, 0] + 0.5) * 2.0 ** -32
+        u2 = (w[:, 1] + 0.5) * 2.0 ** -32
+        return sd * np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
     return rng.normal(0.0, sd, size=n)
 
 
@@ -109,11 +158,12 @@ def surface_fits(betas=(0.5, 1.0), n_strikes=25, moneyness=0.6):
 
 
 def surface_true_params(n_fits, seed=0x5AB2, model=STATIC):
-    """Per-fit generator of true parameters uniform in the box (a fit whose
-    surface is not finite and positive takes the next draw of its own
-    generator)."""
+    """Per-fit stream of true parameters uniform in the box: fit k draws from
+    Philox4x32-10 under key `seed` at counter (k, redraw, 0, 4), so a fit whose
+    surface is not finite and positive takes the next redraw of its own
+    stream."""
     lb, ub = box(model)
-    return [np.random.Generator(np.random.PCG64([seed, k])) for k in range(n_fits)], lb, ub
+    return [PhiloxStream(seed, k, TAG_TRUE) for k in range(n_fits)], lb, ub
 
 
 def mc_grid(f0=1.0, n_strikes=15, vol_scale=0.2):

@@ -340,7 +340,7 @@ def smile_request(S, oracle, x_true, noise_sd, prec, n_chains, n_iters, seed, po
     m = omkt(oracle, g)
     tgt = oracle.model_vols(m, oracle.STATIC, x_true, g.meta["beta"])
     if noise_sd:
-        tgt = tgt + inputs.vol_noise(np.random.default_rng(noise_seed), len(tgt), noise_sd)
+        tgt = tgt + inputs.vol_noise(noise_seed, len(tgt), noise_sd)
     m.target = tgt
     lb, ub = inputs.box(inputs.STATIC)
     req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, g.meta["beta"], lb, ub),

@@ -750,7 +750,7 @@ def _smile_market(oracle, x_true, noise_sd=0.0, seed=1):
     m = oracle.Market(g.T, g.fwd, g.offs, g.K)
     vols = oracle.model_vols(m, oracle.STATIC, x_true, g.meta["beta"])
     if noise_sd:
-        vols = vols + inputs.vol_noise(np.random.default_rng(seed), len(vols), noise_sd)
+        vols = vols + inputs.vol_noise(seed, len(vols), noise_sd)
     m.target = vols
     return m, g
 
