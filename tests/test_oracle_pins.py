@@ -111,6 +111,30 @@ def test_hagan_symmetric_smile_rho0_beta1(oracle, l):
     assert c < d
 
 
+@pytest.mark.parametrize("al,rho,c,T", [(0.2017, -0.8854, 0.9296, 7.0), (0.4528, -0.838, 2.8176, 3.0),
+                                         (0.1, -0.9, 3.0, 10.0), (0.25, -0.6, 2.0, 5.0)])
+def test_hagan_beta1_second_exact_root(oracle, al, rho, c, T):
+    """beta = 1: with rho and c = nu/alpha held, z = c ln(f/K) and z/x(z) do
+    not move, and eq. "haganf" is z/x(z) times alpha + k alpha^3 with
+    k = T (rho c / 4 + (2 - 3 rho^2) c^2 / 24).  For k < 0 the other positive
+    root of a^2 + alpha a + alpha^2 + 1/k = 0 gives the same vol at every
+    strike (the formula is not injective in alpha); a wrong coefficient or a
+    dropped term of the time correction breaks the equality, and so does a
+    z/x(z) that depends on alpha otherwise than through z."""
+    f = 1.3
+    k = T * (rho * c / 4.0 + (2.0 - 3.0 * rho * rho) * c * c / 24.0)
+    assert k < 0
+    a2 = 0.5 * (-al + math.sqrt(-3.0 * al * al - 4.0 / k))
+    assert a2 > 0 and abs(a2 - al) > 0.05
+    for K in f * np.exp(np.linspace(-0.6, 0.6, 13)):
+        v1 = oracle.sigma_hagan(K, f, T, al, 1.0, rho, c * al)
+        v2 = oracle.sigma_hagan(K, f, T, a2, 1.0, rho, c * a2)
+        assert v1 > 0 and v2 == pytest.approx(v1, rel=1e-13)
+    # off the line (nu not scaled with alpha) the two differ
+    assert oracle.sigma_hagan(0.8 * f, f, T, a2, 1.0, rho, c * al) != pytest.approx(
+        oracle.sigma_hagan(0.8 * f, f, T, al, 1.0, rho, c * al), rel=1e-6)
+
+
 def test_hagan_normal_limit_is_bachelier(oracle):
     """beta = 0, nu -> 0: the model is F_T = f + alpha W_T (Bachelier), whose
     call price has a closed form.  Eq. "haganf" is the small-T expansion of
