@@ -593,15 +593,16 @@ int lanes_per_chain(const sabr_ctx *c, const sabr_request &q) {
     return q.sa.n_chains >= 1024 ? 2 : 1;
 }
 
-// Lanes of a group that split the maturity rows (the rest split the strikes of
-// a row): the largest power of two up to the group size that leaves at least
-// two rows per lane.  The static z-form formulas split strikes only.
+// How the lanes of a group share the maturity rows.  0: whole rounds of one
+// row per lane, then the remaining rows over the smallest power of two of
+// lanes that holds them, the other lanes splitting their strikes.  A fixed
+// split r (SABR_ROW_SPLIT) gives lane s the rows s % r (mod r) and the
+// strikes of each such row to the LPC / r lanes that share it.  The static
+// z-form formulas split strikes only.
 int row_split(const sabr_ctx *c, const sabr_request &q, int lpc) {
     if (lpc == 1 || q.problem.model == SABR_STATIC) return 1;
     if (c->force_rsplit) return std::min(c->force_rsplit, lpc);
-    int rs = 1;
-    while (rs < lpc && 2 * (rs * 2) <= q.market.n_mat) rs *= 2;
-    return rs;
+    return 0;
 }
 
 // A request spread over several workgroups needs them all resident at once
@@ -697,10 +698,15 @@ int plan_group(sabr_ctx *c, const sabr_request *reqs, const Group &grp, GroupPla
             g = g * cL;
         }
         d.n_wg = (q.sa.n_chains + chains_per_wg - 1) / chains_per_wg;
+        if (d.n_wg > kMaxReaders * kWG)
+            return fail(c, SABR_E_BUDGET, "request %d spans %d annealing workgroups (at most %d)", r, d.n_wg,
+                        kMaxReaders * kWG);
         d.wg_first = (int)pl.wg_req.size();
         for (int w = 0; w < d.n_wg; ++w) pl.wg_req.push_back(r);
         d.cand_off = pl.cand_slots;
-        pl.cand_slots += 2 * d.n_wg + 2;   // two halves of candidates, two result slots
+        // two halves of candidates, then for each round parity the result
+        // slots of the reader workgroups (one per kWG candidates, wide requests)
+        pl.cand_slots += 2 * d.n_wg + 2 * ((d.n_wg + kWG - 1) / kWG);
         if (d.polish) pl.pol.push_back(r);
         pl.multi_wg |= d.n_wg > 1;
     }

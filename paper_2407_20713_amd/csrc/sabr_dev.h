@@ -18,6 +18,7 @@ namespace sabr {
 
 constexpr int kMaxPar = 10;
 constexpr int kWG = 256;            // threads per annealing workgroup (4 waves)
+constexpr int kMaxReaders = 8;      // workgroups that read a wide request's candidates (kWG each)
 constexpr float kLn2f = 0.693147180559945309f;
 constexpr double kLn2 = 0.693147180559945309417232121458;
 constexpr double kZIsland = 0.05;   // |z| below which x(z)/z comes from its series
@@ -39,7 +40,7 @@ struct ReqDesc {
     int32_t wg_first, n_wg;   // workgroups of this request in the launch
     int32_t cand_off;     // first candidate slot (2 * n_wg slots)
     int32_t polish;
-    int32_t rsplit;       // lanes per chain that split the maturity rows (divides the lane count)
+    int32_t rsplit;       // row split of a lane group: 0 rounds of one row per lane, else a fixed split dividing the lane count
     int32_t spin_limit;   // polls of a level-end slot before the wait gives up
     uint32_t key0, key1;
     double beta;

@@ -291,10 +291,10 @@ __device__ __forceinline__ bool vol_ok(R sig) { return sig > (R)0 && sig < (R)__
 // vector, gives +inf.  WRITE stores the model vols to out[0..n_pts).
 // With LPC > 1 lanes per parameter vector, lane `sub` returns a partial sum.
 // The static z-form loop splits the points of every row over the lanes; the
-// other formulas split the rows over `rsplit` lanes (lane sub % rsplit takes
-// rows i = sub % rsplit (mod rsplit)) and the points of each row over the
-// remaining LPC / rsplit lanes, so that a row's integrals are computed by
-// fewer lanes than its points.
+// other formulas give each lane whole rows where they can, so that a row's
+// integrals are computed by fewer lanes than its points (rsplit 0), or split
+// the rows over `rsplit` lanes and the points of each row over the other
+// LPC / rsplit lanes.
 template <int MODEL, int FORMULA, typename R, bool BFREE, bool WRITE, int LPC = 1, typename P = double>
 __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, int n_mat,
                             double beta_fixed, double t_max, double *out, int sub = 0, int rsplit = 1,
@@ -417,8 +417,6 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         const double acc = acc_a + acc_b;
         return (cmin > 0 && acc < __builtin_inf()) ? acc : __builtin_inf();
     }
-    const int RS = LPC == 1 ? 1 : rsplit, PS = LPC == 1 ? 1 : LPC / rsplit;
-    const int rsub = LPC == 1 ? 0 : sub % RS, psub = LPC == 1 ? 0 : sub / RS;
     // float: two points per step with their own partial sums (two independent
     // dependency chains), added once at the end; residuals in float, their
     // squares summed in double (so the sum hardly depends on how the points
@@ -431,35 +429,73 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
     constexpr bool kIntMin = kTwo && !WRITE;
     int cmin = 0x7fffffff;
     double acc1 = 0.0, acc2 = 0.0;
-    for (int i = rsub; i < n_mat; i += RS) {
+    auto take = [&](const Pt<R> &p, R sig, double &acc) {
+        if constexpr (kIntMin)
+            cmin = min(cmin, __builtin_bit_cast(int, (float)sig));
+        else
+            bad |= !vol_ok(sig);
+        const double e = (double)fma(-sig, p.sw, p.tsw);
+        acc = fma(e, e, acc);
+    };
+    // points first, first + step, ... of row i; in float four at a time (the
+    // four records read together, one LDS wait per four points), then a pair,
+    // then one
+    auto row_points = [&](int i, int first, int step) {
         const Row<R> rw = rows[i];
         ev.row(rw);
-        int j = rw.p0 + psub;
-        for (; kTwo && j + PS < rw.p1; j += 2 * PS) {
-            const Pt<R> pa = pts[j], pb = pts[j + PS];
-            const R sa = ev.point(pa), sb = ev.point(pb);
-            if constexpr (kIntMin)
-                cmin = min(min(cmin, __builtin_bit_cast(int, (float)sa)), __builtin_bit_cast(int, (float)sb));
-            else
-                bad |= !vol_ok(sa) || !vol_ok(sb);
-            const double ea = (double)fma(-sa, pa.sw, pa.tsw), eb = (double)fma(-sb, pb.sw, pb.tsw);
-            acc1 = fma(ea, ea, acc1);
-            acc2 = fma(eb, eb, acc2);
+        int j = rw.p0 + first;
+        for (; kTwo && j + 3 * step < rw.p1; j += 4 * step) {
+            const Pt<R> pa = pts[j], pb = pts[j + step], pc = pts[j + 2 * step], pd = pts[j + 3 * step];
+            const R sa = ev.point(pa), sb = ev.point(pb), sc = ev.point(pc), sd = ev.point(pd);
+            take(pa, sa, acc1);
+            take(pb, sb, acc2);
+            take(pc, sc, acc1);
+            take(pd, sd, acc2);
             if (WRITE) {
                 out[j] = (double)sa;
-                out[j + PS] = (double)sb;
+                out[j + step] = (double)sb;
+                out[j + 2 * step] = (double)sc;
+                out[j + 3 * step] = (double)sd;
             }
         }
-        for (; j < rw.p1; j += PS) {
+        if (kTwo && j + step < rw.p1) {
+            const Pt<R> pa = pts[j], pb = pts[j + step];
+            const R sa = ev.point(pa), sb = ev.point(pb);
+            take(pa, sa, acc1);
+            take(pb, sb, acc2);
+            if (WRITE) {
+                out[j] = (double)sa;
+                out[j + step] = (double)sb;
+            }
+            j += 2 * step;
+        }
+        for (; j < rw.p1; j += step) {
             const Pt<R> p = pts[j];
             const R sig = ev.point(p);
-            if constexpr (kIntMin)
-                cmin = min(cmin, __builtin_bit_cast(int, (float)sig));
-            else
-                bad |= !vol_ok(sig);
-            const double e = (double)fma(-sig, p.sw, p.tsw);
-            acc1 = fma(e, e, acc1);
+            take(p, sig, acc1);
             if (WRITE) out[j] = (double)sig;
+        }
+    };
+    if (LPC == 1) {
+        for (int i = 0; i < n_mat; ++i) row_points(i, 0, 1);
+    } else if (rsplit > 0) {
+        // fixed split: lane sub % rsplit takes rows sub % rsplit (mod rsplit),
+        // the other LPC / rsplit lanes of the row split its points
+        const int RS = rsplit, PS = LPC / rsplit;
+        for (int i = sub % RS; i < n_mat; i += RS) row_points(i, sub / RS, PS);
+    } else {
+        // whole rounds of LPC rows, one row per lane with all its points; the
+        // remaining rows (fewer than LPC) over the smallest power of two of
+        // lanes that holds them, the other lanes of each such row splitting its
+        // points.  Fewer row blocks and fewer points per lane than any fixed
+        // split when the rows are not a multiple of the group size.
+        int i0 = 0;
+        for (; i0 + LPC <= n_mat; i0 += LPC) row_points(i0 + sub, 0, 1);
+        const int rem = n_mat - i0;
+        if (rem > 0) {
+            int rs = 1;
+            while (rs < rem) rs *= 2;
+            if (sub % rs < rem) row_points(i0 + sub % rs, sub / rs, LPC / rs);
         }
     }
     if constexpr (kTwo) acc1 = acc1 + acc2;

@@ -211,6 +211,7 @@ struct ArgminSmem {
     int fail;   // a wait of the exchange timed out
     double bx[kMaxPar];
     double wx[kWG / 64][kMaxPar];   // each wave's winner (exchange read by a whole workgroup)
+    uint32_t rp[kMaxReaders][3 + 2 * kMaxPar];   // the reader workgroups' results
 };
 
 // Level-end argmin over every chain of the request (workgroups of one request
@@ -222,11 +223,13 @@ struct ArgminSmem {
 // r).  The first wave of each workgroup publishes its candidate as tagged
 // words (lane k stores word k).  Up to 64 workgroups, the first wave of each
 // then watches the request's slots (lane w slot w), reading every word of a
-// slot at once until all show the round.  Beyond 64, the request's first
-// workgroup alone reads the slots (thread t slots t, t + 256, ...), takes the
-// argmin and publishes it in the round's result slot (two of them, by round
-// parity), which the other workgroups watch: the same result with traffic
-// linear, not quadratic, in the workgroups.  Returns false, with *err set,
+// slot at once until all show the round.  Beyond 64, each of the request's
+// first R = ceil(workgroups / 256) workgroups reads 256 slots (one per
+// thread), takes their argmin and publishes it in its result slot (R of
+// them for each round parity); every workgroup then reads the R results
+// (thread r result r) and takes their argmin: the same result with traffic
+// linear, not quadratic, in the workgroups, two trips after the last
+// candidate is published.  Returns false, with *err set,
 // if a slot did not show the round within the wait bound (the caller then
 // ends).
 template <int NP>
@@ -298,38 +301,32 @@ __device__ inline bool request_argmin(double f, int chain, bool active, const do
         if (threadIdx.x < NW)
             __hip_atomic_store(&half[wg_local].w[threadIdx.x], tag | word_of(threadIdx.x), __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
-        // the lanes that read slots (the first wave, one slot each, for up to
-        // 64 workgroups; beyond that the first workgroup reads every slot with
-        // all its threads and publishes the winner in a result slot that the
-        // others read: two more trips, but traffic linear in the workgroups)
+        // the lanes that read candidate slots: for up to 64 workgroups the
+        // first wave of every workgroup (lane w slot w); beyond that the
+        // threads of the first R workgroups (thread t of workgroup r slot
+        // 256 r + t), each of which publishes its argmin in a result slot
         const bool direct = rq.n_wg <= 64;
-        const bool reader = direct ? threadIdx.x < 64 : wg_local == 0;
+        const int nr = direct ? 0 : (rq.n_wg + (int)blockDim.x - 1) / (int)blockDim.x;
+        Cand *res = cands + rq.cand_off + 2 * rq.n_wg + (round & 1) * nr;
+        const bool reader = direct ? threadIdx.x < 64 : wg_local < nr;
         if (reader) {
-            const int stride = direct ? 64 : (int)blockDim.x;
             double cf = __builtin_inf();
             int cid = 0x7fffffff;
             double cx[NP];
 #pragma unroll
             for (int k = 0; k < NP; ++k) cx[k] = 0.0;
-            bool timed_out = false;
-            for (int w = threadIdx.x; w < rq.n_wg; w += stride) {
+            const int w = (direct ? 0 : wg_local * (int)blockDim.x) + (int)threadIdx.x;
+            if (w < rq.n_wg) {
                 uint32_t pay[NW];
-                if (!poll(&half[w], pay)) {
-                    timed_out = true;
-                    break;
-                }
-                const double fw = pay_f(pay);
-                const int iw = (int)pay[2];
-                if (fw < cf || (fw == cf && iw < cid)) {
-                    cf = fw;
-                    cid = iw;
+                if (poll(&half[w], pay)) {
+                    cf = pay_f(pay);
+                    cid = (int)pay[2];
 #pragma unroll
                     for (int k = 0; k < NP; ++k) cx[k] = pay_x(pay, k);
+                } else {
+                    __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    s.fail = 1;
                 }
-            }
-            if (timed_out) {
-                __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s.fail = 1;
             }
             int key = cid;
             double kf = cf;
@@ -344,7 +341,7 @@ __device__ inline bool request_argmin(double f, int chain, bool active, const do
                     s.bid = key;
                 }
             } else {
-                // every wave's winner, then the workgroup's, then the result slot
+                // every wave's winner, then the workgroup's, then its result slot
                 const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
                 if (lane == src) {
                     s.wf[wave] = kf;
@@ -363,18 +360,26 @@ __device__ inline bool request_argmin(double f, int chain, bool active, const do
                 }
                 __syncthreads();
                 if (threadIdx.x < NW)
-                    __hip_atomic_store(&cands[rq.cand_off + 2 * rq.n_wg + (round & 1)].w[threadIdx.x],
-                                       tag | word_of(threadIdx.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&res[wg_local].w[threadIdx.x], tag | word_of(threadIdx.x), __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
             }
-        } else if (!direct && threadIdx.x == 0) {
-            uint32_t pay[NW];
-            if (poll(&cands[rq.cand_off + 2 * rq.n_wg + (round & 1)], pay)) {
-                s.bf = pay_f(pay);
-                s.bid = (int)pay[2];
-                for (int k = 0; k < NP; ++k) s.bx[k] = pay_x(pay, k);
-            } else {
+        }
+        if (!direct) {
+            // the R results, one per thread, then their argmin
+            if ((int)threadIdx.x < nr && !poll(&res[threadIdx.x], s.rp[threadIdx.x])) {
                 __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 s.fail = 1;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0 && s.fail == 0) {
+                int br = 0;
+                for (int r = 1; r < nr; ++r) {
+                    const double fr = pay_f(s.rp[r]), fb = pay_f(s.rp[br]);
+                    if (fr < fb || (fr == fb && (int)s.rp[r][2] < (int)s.rp[br][2])) br = r;
+                }
+                s.bf = pay_f(s.rp[br]);
+                s.bid = (int)s.rp[br][2];
+                for (int k = 0; k < NP; ++k) s.bx[k] = pay_x(s.rp[br], k);
             }
         }
         __syncthreads();
