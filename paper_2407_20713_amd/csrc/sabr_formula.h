@@ -223,6 +223,13 @@ struct ModelEval {
                 case2_integrals(fp, Td, np, ints);
                 q = dynamic_block<R>(F1, rw.T, al, beta, (R)ints[0], (R)ints[1], (R)ints[2], (R)ints[3]);
             }
+            if constexpr (sizeof(R) == 4) {
+                // float: inv_w folded into the row's coefficients (one
+                // multiplication per row instead of one per point)
+                q.A1 *= q.inv_w;
+                q.A2 *= q.inv_w;
+                q.c0 *= q.inv_w;
+            }
         }
     }
 
@@ -277,6 +284,7 @@ struct ModelEval {
             return al * P1 * zx * corr;
         } else {
             const R L = -p.lfk;
+            if constexpr (sizeof(R) == 4) return fma(L, fma(q.A2, L, q.A1), q.c0);   // inv_w folded in
             return q.inv_w * fma(L, fma(q.A2, L, q.A1), q.c0);
         }
     }
