@@ -242,19 +242,22 @@ __host__ __device__ constexpr double pow2(int n) {
 // chain (the reference evaluation order of the double path).
 template <typename R, int NT, typename C>
 __device__ __forceinline__ R series_even_odd(R z, C c) {
+    static_assert(NT >= 2, "at least two terms");
     if constexpr (sizeof(R) == 8) {
-        R h = 0;
+        R h = (R)c(NT - 1);
 #pragma unroll
-        for (int k = NT - 1; k >= 0; --k) h = h * z + (R)c(k);
+        for (int k = NT - 2; k >= 0; --k) h = h * z + (R)c(k);
         return h;
     } else {
+        // even terms up to 2 JE, odd terms up to 2 JO + 1, each chain started
+        // at its top coefficient
+        constexpr int JE = (NT - 1) / 2, JO = (NT - 2) / 2;
         const R u = z * z;
-        R e = 0, o = 0;
+        R e = (R)c(2 * JE), o = (R)c(2 * JO + 1);
 #pragma unroll
-        for (int j = (NT - 1) / 2; j >= 0; --j) {
-            if (2 * j + 1 < NT) o = o * u + (R)c(2 * j + 1);
-            e = e * u + (R)c(2 * j);
-        }
+        for (int j = JE - 1; j >= 0; --j) e = e * u + (R)c(2 * j);
+#pragma unroll
+        for (int j = JO - 1; j >= 0; --j) o = o * u + (R)c(2 * j + 1);
         return e + z * o;
     }
 }

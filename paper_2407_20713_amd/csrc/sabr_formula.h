@@ -425,7 +425,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         const double acc = acc_a + acc_b;
         return (cmin > 0 && acc < __builtin_inf()) ? acc : __builtin_inf();
     }
-    // float: two points per step with their own partial sums (two independent
+    // float: points in pairs with their own partial sums (two independent
     // dependency chains), added once at the end; residuals in float, their
     // squares summed in double (so the sum hardly depends on how the points
     // are split over lanes); double: one sum in point order
