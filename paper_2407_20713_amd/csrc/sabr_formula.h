@@ -435,6 +435,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
     // at or below 0; +inf and NaN make the sum infinite or NaN), one integer
     // minimum per point instead of two tests
     constexpr bool kIntMin = kTwo && !WRITE;
+    constexpr bool kFour = kTwo && MODEL != MODEL_STATIC;
     int cmin = 0x7fffffff;
     double acc1 = 0.0, acc2 = 0.0;
     auto take = [&](const Pt<R> &p, R sig, double &acc) {
@@ -445,14 +446,15 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         const double e = (double)fma(-sig, p.sw, p.tsw);
         acc = fma(e, e, acc);
     };
-    // points first, first + step, ... of row i; in float four at a time (the
-    // four records read together, one LDS wait per four points), then a pair,
+    // points first, first + step, ... of row i; in float four at a time
+    // where the model's row blocks leave the registers for it (the four
+    // records read together, one LDS wait per four points), then in pairs,
     // then one
     auto row_points = [&](int i, int first, int step) {
         const Row<R> rw = rows[i];
         ev.row(rw);
         int j = rw.p0 + first;
-        for (; kTwo && j + 3 * step < rw.p1; j += 4 * step) {
+        for (; kFour && j + 3 * step < rw.p1; j += 4 * step) {
             const Pt<R> pa = pts[j], pb = pts[j + step], pc = pts[j + 2 * step], pd = pts[j + 3 * step];
             const R sa = ev.point(pa), sb = ev.point(pb), sc = ev.point(pc), sd = ev.point(pd);
             take(pa, sa, acc1);
@@ -466,16 +468,23 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
                 out[j + 3 * step] = (double)sd;
             }
         }
-        if (kTwo && j + step < rw.p1) {
-            const Pt<R> pa = pts[j], pb = pts[j + step];
+        auto pair = [&](int jj) {
+            const Pt<R> pa = pts[jj], pb = pts[jj + step];
             const R sa = ev.point(pa), sb = ev.point(pb);
             take(pa, sa, acc1);
             take(pb, sb, acc2);
             if (WRITE) {
-                out[j] = (double)sa;
-                out[j + step] = (double)sb;
+                out[jj] = (double)sa;
+                out[jj + step] = (double)sb;
             }
-            j += 2 * step;
+        };
+        if constexpr (kFour) {
+            if (j + step < rw.p1) {   // at most one pair after the fours
+                pair(j);
+                j += 2 * step;
+            }
+        } else {
+            for (; kTwo && j + step < rw.p1; j += 2 * step) pair(j);
         }
         for (; j < rw.p1; j += step) {
             const Pt<R> p = pts[j];
