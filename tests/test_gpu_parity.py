@@ -466,13 +466,20 @@ def _ctx_with(S, env):
                 os.environ[k] = v
 
 
-@pytest.mark.parametrize("model,n_chains", [(inputs.DYN_I, 2048), (inputs.DYN_II, 2048), (inputs.DYN_I, 300)])
-def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model, n_chains):
+@pytest.mark.parametrize("model,n_chains,ragged", [(inputs.DYN_I, 2048, False), (inputs.DYN_II, 2048, False),
+                                                   (inputs.DYN_I, 300, False), (inputs.DYN_I, 1024, True)])
+def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model, n_chains, ragged):
     """Float dynamic requests of many chains spread each chain over up to 16
-    lanes (rows and strikes split); only the order of the double partial sums
-    changes, so the accept decisions and the result are those of one lane per
-    chain, for every row split."""
-    if model == inputs.DYN_I:
+    lanes (whole rows per lane, the remaining rows split, or a fixed row
+    split); only the order of the double partial sums changes, so the accept
+    decisions and the result are those of one lane per chain, for every
+    schedule (the ragged grid: 13 rows of 5 to 21 strikes, fewer rows than a
+    16-lane group)."""
+    if ragged:
+        T = inputs.dynamic_ladder(20)[:13]
+        g = inputs.make_grid(T, [np.exp(np.linspace(-0.5, 0.5, 5 + (3 * i) % 17)) for i in range(13)])
+        xt = inputs.dynamic_surface().meta["x_true"]
+    elif model == inputs.DYN_I:
         g = inputs.dynamic_surface()
         xt = g.meta["x_true"]
     else:
@@ -486,7 +493,8 @@ def test_sa_wide_lane_groups_follow_one_lane_trajectory(S, ctx, oracle, model, n
     runs = {}
     for name, env in (("one", {"SABR_LANES_PER_CHAIN": "1"}), ("default", {}),
                       ("16x16", {"SABR_LANES_PER_CHAIN": "16", "SABR_ROW_SPLIT": "16"}),
-                      ("8x2", {"SABR_LANES_PER_CHAIN": "8", "SABR_ROW_SPLIT": "2"})):
+                      ("8x2", {"SABR_LANES_PER_CHAIN": "8", "SABR_ROW_SPLIT": "2"}),
+                      ("16", {"SABR_LANES_PER_CHAIN": "16"}), ("4", {"SABR_LANES_PER_CHAIN": "4"})):
         c = _ctx_with(S, env) if env else ctx
         say("wide lanes", model, name)
         runs[name] = S.sabr_calibrate(c, req)
