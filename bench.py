@@ -148,9 +148,15 @@ def mc_path_steps(S, ctx, n_paths=1 << 24):
     wall = time.perf_counter() - t
     ms, n, _ = S.sabr_ctx_timing(ctx, reset=True)
     steps = 123
+    # the same call on antithetic pairs (a variance reduction the paper does
+    # not use): its error against the plain scheme's on as many paths
+    pa, sa = S.sabr_mc_price(ctx, S.Market.from_grid(g), pb, n_paths, scheme=S.SABR_MC_ANTITHETIC)
+    ms_a, _, _ = S.sabr_ctx_timing(ctx, reset=True)
     return dict(workload="European call, case I, 2^24 paths x 123 steps, fp32", price=float(p[0]),
                 std_err=float(se[0]), kernel_ms=ms, wall_ms=wall * 1e3,
-                path_steps_per_s=n_paths * steps / (ms / 1e3))
+                path_steps_per_s=n_paths * steps / (ms / 1e3),
+                antithetic={"price": float(pa[0]), "std_err": float(sa[0]), "kernel_ms": ms_a,
+                            "variance_ratio": float((se[0] / sa[0]) ** 2)})
 
 
 def cpu_model():

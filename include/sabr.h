@@ -123,10 +123,18 @@ typedef struct {
  * dt = 1/steps_per_year; maturity i is read at step max(1, floor(T_i / dt)).
  * Normals by Box-Muller from Philox4x32-10 keyed by seed, counter
  * (path, step/2, 0, 2).  All maturities of a grid share the paths, so the
- * grid must have a single forward. */
+ * grid must have a single forward.
+ * scheme: SABR_MC_PLAIN, or SABR_MC_ANTITHETIC (variance reduction, not in
+ * the paper): paths come in pairs, path 2k drawing counter (k, step/2, 0, 2)
+ * and path 2k + 1 the same normals negated; n_paths must be even, prices
+ * are the mean over all paths and standard errors come from the n_paths / 2
+ * pair means.  Other values are rejected with SABR_E_INVAL; the serving
+ * loop takes the plain scheme only. */
+enum { SABR_MC_PLAIN = 0, SABR_MC_ANTITHETIC = 1 };
 typedef struct {
     int64_t n_paths;
     int32_t steps_per_year;
+    int32_t scheme;
     uint64_t seed;
 } sabr_mc;
 

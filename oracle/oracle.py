@@ -19,6 +19,7 @@ STATIC, DYN_I, DYN_II = 0, 1, 2
 HAGAN, OBLOJ, EXPANSION = 0, 1, 2
 ABSOLUTE, RELATIVE = 0, 1
 OBJ_FORMULA, OBJ_MC = 0, 1
+MC_PLAIN, MC_ANTITHETIC = 0, 1
 
 
 def build(force=False):
@@ -46,7 +47,8 @@ class SAProblem(C.Structure):
                 ("n_chains", C.c_int32), ("n_iters", C.c_int32), ("chain_len", C.c_int32),
                 ("T0", C.c_double), ("cooling", C.c_double), ("step0", C.c_double),
                 ("step_min", C.c_double), ("seed", C.c_uint64), ("polish", C.c_int32),
-                ("mc_paths", C.c_int64), ("mc_steps_per_year", C.c_int32), ("mc_seed", C.c_uint64)]
+                ("mc_paths", C.c_int64), ("mc_steps_per_year", C.c_int32), ("mc_scheme", C.c_int32),
+                ("mc_seed", C.c_uint64)]
 
 
 class SAResult(C.Structure):
@@ -61,6 +63,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         L.or_philox4x32_10.argtypes = [_U32, _U32, _U32]
         L.or_mc_normals.argtypes = [C.c_uint64, C.c_int64, C.c_int32, _D, _D]
+        L.or_path_normals.argtypes = [C.c_uint64, C.c_int, C.c_int64, C.c_int32, _D, _D]
         for name in ("or_sigma_hagan", "or_sigma_obloj", "or_sigma_expansion"):
             getattr(L, name).argtypes = [C.c_double] * 7
             getattr(L, name).restype = C.c_double
@@ -79,14 +82,14 @@ def lib():
                                            _D, C.c_int, _D, _D, _I32, _D, _D]
         L.or_objective_formula.restype = C.c_double
         L.or_mc_prices.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _D, C.c_int, _D, _D, _D,
-                                   _I32, _D, C.c_int64, C.c_int32, C.c_uint64, _D, _D]
+                                   _I32, _D, C.c_int64, C.c_int32, C.c_uint64, C.c_int, _D, _D]
         L.or_objective_mc.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, _D, C.c_int,
-                                      _D, _D, _D, _I32, _D, _D, C.c_int64, C.c_int32, C.c_uint64]
+                                      _D, _D, _D, _I32, _D, _D, C.c_int64, C.c_int32, C.c_uint64, C.c_int]
         L.or_objective_mc.restype = C.c_double
         L.or_case2_feasible.argtypes = [_D, C.c_double]
         L.or_mc_cliquet.argtypes = [C.c_int, C.c_double, C.c_int, C.c_int, _D, C.c_double, C.c_double, C.c_int,
                                     _D, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int32,
-                                    C.c_uint64, _D, _D]
+                                    C.c_uint64, C.c_int, _D, _D]
         L.or_atm_vol.argtypes = [C.c_int, _D, _D, C.c_double]
         L.or_atm_vol.restype = C.c_double
         L.or_beta_from_atm.argtypes = [C.c_int, _D, _D, _D, _D]
@@ -119,6 +122,12 @@ def philox(ctr, key):
     o = (C.c_uint32 * 4)()
     lib().or_philox4x32_10(c, k, o)
     return [int(v) for v in o]
+
+
+def path_normals(seed, scheme, path, step):
+    z1, z2 = C.c_double(), C.c_double()
+    lib().or_path_normals(seed, scheme, path, step, C.byref(z1), C.byref(z2))
+    return z1.value, z2.value
 
 
 def mc_normals(seed, path, step):
@@ -213,37 +222,38 @@ def objective_formula(market, model, x, beta, beta_free=False, formula=HAGAN, we
                                       _dp(market.target))
 
 
-def mc_prices(market, model, x, beta, n_paths, steps_per_year, seed, beta_free=False):
+def mc_prices(market, model, x, beta, n_paths, steps_per_year, seed, beta_free=False, scheme=0):
     x = _f64(x)
     price = np.zeros(market.n_obs)
     se = np.zeros(market.n_obs)
     rc = lib().or_mc_prices(model, beta, int(beta_free), len(x), _dp(x), market.n_mat,
                             _dp(market.T), _dp(market.fwd), _dp(market.disc),
                             market.offs.ctypes.data_as(_I32), _dp(market.K), int(n_paths),
-                            int(steps_per_year), int(seed), _dp(price), _dp(se))
+                            int(steps_per_year), int(seed), int(scheme), _dp(price), _dp(se))
     if rc:
         raise ValueError("or_mc_prices failed")
     return price, se
 
 
 def objective_mc(market, model, x, beta, n_paths, steps_per_year, seed, beta_free=False,
-                 weighting=RELATIVE):
+                 weighting=RELATIVE, scheme=0):
     x = _f64(x)
     return lib().or_objective_mc(model, weighting, beta, int(beta_free), len(x), _dp(x),
                                  market.n_mat, _dp(market.T), _dp(market.fwd), _dp(market.disc),
                                  market.offs.ctypes.data_as(_I32), _dp(market.K),
-                                 _dp(market.target), int(n_paths), int(steps_per_year), int(seed))
+                                 _dp(market.target), int(n_paths), int(steps_per_year), int(seed),
+                                 int(scheme))
 
 
 def mc_cliquet(model, x, beta, f0, reset_T, local_floor, local_cap, global_floor, global_cap, n_paths,
-               steps_per_year, seed, disc=1.0, beta_free=False):
+               steps_per_year, seed, disc=1.0, beta_free=False, scheme=0):
     """Cliquet price and standard error on the paths of mc_prices."""
     x = _f64(x)
     rt = _f64(reset_T)
     price, se = C.c_double(), C.c_double()
     rc = lib().or_mc_cliquet(model, beta, int(beta_free), len(x), _dp(x), f0, disc, len(rt), _dp(rt),
                              local_floor, local_cap, global_floor, global_cap, int(n_paths), int(steps_per_year),
-                             int(seed), C.byref(price), C.byref(se))
+                             int(seed), int(scheme), C.byref(price), C.byref(se))
     if rc:
         raise ValueError("or_mc_cliquet failed")
     return price.value, se.value
@@ -281,7 +291,7 @@ class _Keep:
 def _problem(market, model, lb, ub, beta, n_chains, n_iters, seed, *, beta_free=False,
              formula=HAGAN, weighting=ABSOLUTE, objective=OBJ_FORMULA, chain_len=10, T0=0.0,
              cooling=None, step0=0.1, step_min=1e-4, polish=False, x0=None, mc_paths=0,
-             mc_steps_per_year=250, mc_seed=0):
+             mc_steps_per_year=250, mc_seed=0, mc_scheme=0):
     keep = _Keep()
     keep.lb, keep.ub = _f64(lb), _f64(ub)
     keep.x0 = None if x0 is None else _f64(x0)
@@ -296,7 +306,7 @@ def _problem(market, model, lb, ub, beta, n_chains, n_iters, seed, *, beta_free=
                    target=_dp(market.target), n_chains=n_chains, n_iters=n_iters,
                    chain_len=chain_len, T0=T0, cooling=cooling, step0=step0, step_min=step_min,
                    seed=seed, polish=int(polish), mc_paths=mc_paths,
-                   mc_steps_per_year=mc_steps_per_year, mc_seed=mc_seed)
+                   mc_steps_per_year=mc_steps_per_year, mc_seed=mc_seed, mc_scheme=mc_scheme)
     return pb, keep
 
 

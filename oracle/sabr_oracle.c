@@ -62,6 +62,19 @@ static double u24(uint32_t w) { return ((double)(w >> 8) + 0.5) * (1.0 / 1677721
 /* Uniform in (0,1) from a whole word, for the annealing decisions. */
 static double u32(uint32_t w) { return ((double)w + 0.5) * (1.0 / 4294967296.0); }
 
+/* The normals of one step of a path under the path scheme: plain, or       */
+/* antithetic pairs, in which paths 2k and 2k + 1 both take the draws of    */
+/* counter k and the odd path negates them.                                 */
+void or_path_normals(uint64_t seed, int scheme, int64_t path, int32_t step, double *z1, double *z2)
+{
+    if (scheme == OR_MC_ANTITHETIC) {
+        or_mc_normals(seed, path / 2, step, z1, z2);
+        if (path % 2 == 1) { *z1 = -*z1; *z2 = -*z2; }
+    } else {
+        or_mc_normals(seed, path, step, z1, z2);
+    }
+}
+
 /* Two independent standard normals for one time step of one path, by the   */
 /* Box-Muller transform the paper uses (Section 4, GPU process, step 2).    */
 void or_mc_normals(uint64_t seed, int64_t path, int32_t step, double *z1, double *z2)
@@ -511,11 +524,13 @@ static void nsum_add(nsum *a, double v)
 int or_mc_prices(int model, double beta, int beta_free, int n_par, const double *x,
                  int n_mat, const double *T, const double *fwd, const double *disc,
                  const int32_t *offs, const double *K, int64_t n_paths, int32_t steps_per_year,
-                 uint64_t seed, double *price, double *std_err)
+                 uint64_t seed, int scheme, double *price, double *std_err)
 {
     or_params p;
     if (unpack(model, beta, beta_free, n_par, x, &p)) return -1;
     if (n_paths < 1 || steps_per_year < 1 || n_mat < 1) return -1;
+    if (scheme != OR_MC_PLAIN && scheme != OR_MC_ANTITHETIC) return -1;
+    if (scheme == OR_MC_ANTITHETIC && n_paths % 2 != 0) return -1;
     for (int i = 1; i < n_mat; ++i) if (fwd[i] != fwd[0]) return -1;
     fn_params q = { p.rho0, p.nu0, p.a, p.b, p.drho, p.dnu, p.qrho, p.qnu, model };
     int n_obs = offs[n_mat];
@@ -523,7 +538,8 @@ int or_mc_prices(int model, double beta, int beta_free, int n_par, const double 
     int32_t *mi = malloc(sizeof(int32_t) * (size_t)n_mat);
     nsum *s1 = calloc((size_t)(n_obs > 0 ? n_obs : 1), sizeof(nsum));
     nsum *s2 = calloc((size_t)(n_obs > 0 ? n_obs : 1), sizeof(nsum));
-    if (!mi || !s1 || !s2) { free(mi); free(s1); free(s2); return -2; }
+    double *v_even = calloc((size_t)(n_obs > 0 ? n_obs : 1), sizeof(double));   /* first payoff of a pair */
+    if (!mi || !s1 || !s2 || !v_even) { free(mi); free(s1); free(s2); free(v_even); return -2; }
     for (int i = 0; i < n_mat; ++i) { mi[i] = n_steps(T[i], steps_per_year); if (mi[i] > m_max) m_max = mi[i]; }
     double dt = 1.0 / (double)steps_per_year;
     double sdt = sqrt(dt);
@@ -534,7 +550,7 @@ int or_mc_prices(int model, double beta, int beta_free, int n_par, const double 
         for (int32_t i = 0; i < m_max; ++i) {
             if (!absorbed) {
                 double z1, z2;
-                or_mc_normals(seed, path, i, &z1, &z2);
+                or_path_normals(seed, scheme, path, i, &z1, &z2);
                 double t = i * dt;
                 double nu = (model == OR_STATIC) ? p.nu0 : fn_nu(&q, t);
                 double rho = (model == OR_STATIC) ? p.rho0 : fn_rho(&q, t);
@@ -550,22 +566,28 @@ int or_mc_prices(int model, double beta, int beta_free, int n_par, const double 
                 if (mi[m] != i + 1) continue;
                 for (int j = offs[m]; j < offs[m + 1]; ++j) {
                     double v = fmax(F - K[j], 0.0);
+                    if (scheme == OR_MC_ANTITHETIC) {
+                        /* one sample per pair: the mean of its two payoffs */
+                        if (path % 2 == 0) { v_even[j] = v; continue; }
+                        v = 0.5 * (v_even[j] + v);
+                    }
                     nsum_add(&s1[j], v);
                     nsum_add(&s2[j], v * v);
                 }
             }
         }
     }
+    const int64_t n_samp = (scheme == OR_MC_ANTITHETIC) ? n_paths / 2 : n_paths;
     for (int m = 0; m < n_mat; ++m) {
         for (int j = offs[m]; j < offs[m + 1]; ++j) {
-            double mean = (s1[j].s + s1[j].c) / (double)n_paths;
-            double ex2 = (s2[j].s + s2[j].c) / (double)n_paths;
-            double var = (n_paths > 1) ? fmax(ex2 - mean * mean, 0.0) * (double)n_paths / (double)(n_paths - 1) : 0.0;
+            double mean = (s1[j].s + s1[j].c) / (double)n_samp;
+            double ex2 = (s2[j].s + s2[j].c) / (double)n_samp;
+            double var = (n_samp > 1) ? fmax(ex2 - mean * mean, 0.0) * (double)n_samp / (double)(n_samp - 1) : 0.0;
             price[j] = disc[m] * mean;
-            if (std_err) std_err[j] = disc[m] * sqrt(var / (double)n_paths);
+            if (std_err) std_err[j] = disc[m] * sqrt(var / (double)n_samp);
         }
     }
-    free(mi); free(s1); free(s2);
+    free(mi); free(s1); free(s2); free(v_even);
     return 0;
 }
 
@@ -584,11 +606,13 @@ int or_mc_prices(int model, double beta, int beta_free, int n_par, const double 
 int or_mc_cliquet(int model, double beta, int beta_free, int n_par, const double *x, double f0, double disc,
                   int n_reset, const double *reset_T, double local_floor, double local_cap,
                   double global_floor, double global_cap, int64_t n_paths, int32_t steps_per_year,
-                  uint64_t seed, double *price, double *std_err)
+                  uint64_t seed, int scheme, double *price, double *std_err)
 {
     or_params p;
     if (unpack(model, beta, beta_free, n_par, x, &p)) return -1;
     if (n_paths < 1 || steps_per_year < 1 || n_reset < 2 || !(f0 > 0.0)) return -1;
+    if (scheme != OR_MC_PLAIN && scheme != OR_MC_ANTITHETIC) return -1;
+    if (scheme == OR_MC_ANTITHETIC && n_paths % 2 != 0) return -1;
     fn_params q = { p.rho0, p.nu0, p.a, p.b, p.drho, p.dnu, p.qrho, p.qnu, model };
     int32_t *ms = malloc(sizeof(int32_t) * (size_t)n_reset);
     if (!ms) return -2;
@@ -600,6 +624,7 @@ int or_mc_cliquet(int model, double beta, int beta_free, int n_par, const double
     double dt = 1.0 / (double)steps_per_year;
     double sdt = sqrt(dt);
     nsum s1 = { 0.0, 0.0 }, s2 = { 0.0, 0.0 };
+    double v_even = 0.0;   /* first payoff of an antithetic pair */
     for (int64_t path = 0; path < n_paths; ++path) {
         double al = p.alpha, F = f0;
         int absorbed = 0, next = 0;
@@ -607,7 +632,7 @@ int or_mc_cliquet(int model, double beta, int beta_free, int n_par, const double
         for (int32_t i = 0; i < m_max; ++i) {
             if (!absorbed) {
                 double z1, z2;
-                or_mc_normals(seed, path, i, &z1, &z2);
+                or_path_normals(seed, scheme, path, i, &z1, &z2);
                 double t = i * dt;
                 double nu = (model == OR_STATIC) ? p.nu0 : fn_nu(&q, t);
                 double rho = (model == OR_STATIC) ? p.rho0 : fn_rho(&q, t);
@@ -629,14 +654,19 @@ int or_mc_cliquet(int model, double beta, int beta_free, int n_par, const double
             }
         }
         double v = fmax(global_floor, fmin(global_cap, sum));
+        if (scheme == OR_MC_ANTITHETIC) {
+            if (path % 2 == 0) { v_even = v; continue; }
+            v = 0.5 * (v_even + v);
+        }
         nsum_add(&s1, v);
         nsum_add(&s2, v * v);
     }
-    double mean = (s1.s + s1.c) / (double)n_paths;
-    double ex2 = (s2.s + s2.c) / (double)n_paths;
-    double var = (n_paths > 1) ? fmax(ex2 - mean * mean, 0.0) * (double)n_paths / (double)(n_paths - 1) : 0.0;
+    const int64_t n_samp = (scheme == OR_MC_ANTITHETIC) ? n_paths / 2 : n_paths;
+    double mean = (s1.s + s1.c) / (double)n_samp;
+    double ex2 = (s2.s + s2.c) / (double)n_samp;
+    double var = (n_samp > 1) ? fmax(ex2 - mean * mean, 0.0) * (double)n_samp / (double)(n_samp - 1) : 0.0;
     *price = disc * mean;
-    if (std_err) *std_err = disc * sqrt(var / (double)n_paths);
+    if (std_err) *std_err = disc * sqrt(var / (double)n_samp);
     free(ms);
     return 0;
 }
@@ -647,13 +677,13 @@ double or_objective_mc(int model, int weighting, double beta, int beta_free, int
                        const double *x, int n_mat, const double *T, const double *fwd,
                        const double *disc, const int32_t *offs, const double *K,
                        const double *target, int64_t n_paths, int32_t steps_per_year,
-                       uint64_t seed)
+                       uint64_t seed, int scheme)
 {
     int n = offs[n_mat];
     double *m = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     if (!m) return NAN;
     if (or_mc_prices(model, beta, beta_free, n_par, x, n_mat, T, fwd, disc, offs, K, n_paths,
-                     steps_per_year, seed, m, NULL)) { free(m); return NAN; }
+                     steps_per_year, seed, scheme, m, NULL)) { free(m); return NAN; }
     double f = 0.0;
     for (int j = 0; j < n; ++j) {
         if (!isfinite(m[j])) { free(m); return INFINITY; }
@@ -796,7 +826,7 @@ static double eval_objective(const or_sa_problem *pb, const double *x)
     else
         f = or_objective_mc(pb->model, pb->weighting, pb->beta, pb->beta_free, pb->n_par, x,
                             pb->n_mat, pb->T, pb->fwd, pb->disc, pb->offs, pb->K, pb->target,
-                            pb->mc_paths, pb->mc_steps_per_year, pb->mc_seed);
+                            pb->mc_paths, pb->mc_steps_per_year, pb->mc_seed, pb->mc_scheme);
     if (!(f == f)) f = INFINITY;  /* NaN ranks last */
     return f;
 }

@@ -35,10 +35,12 @@ enum { OR_STATIC = 0, OR_DYN_I = 1, OR_DYN_II = 2 };
 enum { OR_F_HAGAN = 0, OR_F_OBLOJ = 1, OR_F_EXPANSION = 2 };
 enum { OR_W_ABSOLUTE = 0, OR_W_RELATIVE = 1 };
 enum { OR_OBJ_FORMULA = 0, OR_OBJ_MC = 1 };
+enum { OR_MC_PLAIN = 0, OR_MC_ANTITHETIC = 1 };   /* path schemes (antithetic pairs: not in the paper) */
 
 /* random numbers */
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void or_mc_normals(uint64_t seed, int64_t path, int32_t step, double *z1, double *z2);
+void or_path_normals(uint64_t seed, int scheme, int64_t path, int32_t step, double *z1, double *z2);
 
 /* implied volatility formulas (one point) */
 double or_z_over_x(double z, double rho);
@@ -62,11 +64,13 @@ double or_objective_formula(int model, int formula, int weighting, double beta, 
                             const double *fwd, const int32_t *offs, const double *K,
                             const double *target);
 
-/* Monte Carlo prices of European calls on one grid (common forward) */
+/* Monte Carlo prices of European calls on one grid (common forward); under */
+/* the antithetic scheme n_paths must be even and the standard error comes  */
+/* from the pair means */
 int or_mc_prices(int model, double beta, int beta_free, int n_par, const double *x,
                  int n_mat, const double *T, const double *fwd, const double *disc,
                  const int32_t *offs, const double *K, int64_t n_paths, int32_t steps_per_year,
-                 uint64_t seed, double *price, double *std_err);
+                 uint64_t seed, int scheme, double *price, double *std_err);
 
 /* cliquet option with local and global limits (Section 6) on the paths of */
 /* or_mc_prices: reset dates reset_T[n_reset] (increasing), returns         */
@@ -75,14 +79,14 @@ int or_mc_prices(int model, double beta, int beta_free, int n_par, const double 
 int or_mc_cliquet(int model, double beta, int beta_free, int n_par, const double *x, double f0, double disc,
                   int n_reset, const double *reset_T, double local_floor, double local_cap,
                   double global_floor, double global_cap, int64_t n_paths, int32_t steps_per_year,
-                  uint64_t seed, double *price, double *std_err);
+                  uint64_t seed, int scheme, double *price, double *std_err);
 
 /* objective of the Monte Carlo technique */
 double or_objective_mc(int model, int weighting, double beta, int beta_free, int n_par,
                        const double *x, int n_mat, const double *T, const double *fwd,
                        const double *disc, const int32_t *offs, const double *K,
                        const double *target, int64_t n_paths, int32_t steps_per_year,
-                       uint64_t seed);
+                       uint64_t seed, int scheme);
 
 /* at-the-money start point (Section 3): the market vol at K = f of one row, */
 /* beta and alpha from a log-log fit of (f, sigma_ATM), the start point x0  */
@@ -111,6 +115,7 @@ typedef struct {
     int32_t polish;
     int64_t mc_paths;
     int32_t mc_steps_per_year;
+    int32_t mc_scheme;
     uint64_t mc_seed;
 } or_sa_problem;
 

@@ -42,15 +42,19 @@ __global__ void __launch_bounds__(256) mc_price_kernel(McDesc d, const int32_t *
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t path = tile * 256 + threadIdx.x;
         const bool active = path < d.n_paths;
+        const bool anti = d.anti != 0;
+        const R sg = path_sign<R>(path, anti);
         R X = 0, A = A0;
         int mi = 0;
         uint4 w = make_uint4(0, 0, 0, 0);
         for (int s = 0; s < d.m_max; ++s) {
-            if ((s & 1) == 0) w = philox4x32_10(make_uint4((uint32_t)path, (uint32_t)(s >> 1), 0u, 2u), d.key0, d.key1);
+            if ((s & 1) == 0) w = path_words(path, (uint32_t)(s >> 1), anti, d.key0, d.key1);
             const R u1 = MC<R>::unit((s & 1) ? w.z : w.x);
             const R u2 = MC<R>::unit((s & 1) ? w.w : w.y);
             R z1, z2;
             MC<R>::normals(u1, u2, z1, z2);
+            z1 *= sg;
+            z2 *= sg;
             const StepC<R> c = st[s];
             const R vh = MC<R>::exp2_(fma(bm1, fmax(X, xabs), A));
             A = fma(c.nz, z1, A + c.nd);
@@ -61,7 +65,13 @@ __global__ void __launch_bounds__(256) mc_price_kernel(McDesc d, const int32_t *
                 const R F = f0 * MC<R>::exp2_(X);
                 for (int o = offs[mi]; o < offs[mi + 1]; ++o) {
                     const double v = active ? (double)fmax(F - Ks[o], (R)0) : 0.0;
+                    // antithetic: one squared sample per pair (its mean, on the
+                    // even lane); a pair is two neighbouring lanes
                     double vs = v, vq = v * v;
+                    if (anti) {   // uniform over the launch
+                        const double pm = 0.5 * (v + __shfl_xor(v, 1, 64));
+                        vq = (lane & 1) ? 0.0 : pm * pm;
+                    }
 #pragma unroll
                     for (int off = 32; off > 0; off >>= 1) {
                         vs += __shfl_xor(vs, off, 64);
@@ -109,7 +119,7 @@ __global__ void mc_grid_kernel(int n_mat, const double *T, const int32_t *offs, 
 
 // Sums of the workgroup partials in a fixed order: price = disc * S / N and
 // its standard error.
-__global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, const double *part_s,
+__global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, int anti, const double *part_s,
                                   const double *part_q, const int32_t *obs_row, const double *disc,
                                   double *price, double *se) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,9 +129,12 @@ __global__ void mc_price_finalize(int n_obs, int n_blocks, int64_t n_paths, cons
         s += part_s[(size_t)b * n_obs + o];
         q += part_q[(size_t)b * n_obs + o];
     }
-    const double N = (double)n_paths;
-    const double mean = s / N;
-    const double var = n_paths > 1 ? fmax(q / N - mean * mean, 0.0) * N / (N - 1.0) : 0.0;
+    // samples: the paths, or the antithetic pairs (q then sums the squared
+    // pair means; their mean is the mean over all paths)
+    const int64_t n_samp = anti ? n_paths / 2 : n_paths;
+    const double N = (double)n_samp;
+    const double mean = s / (double)n_paths;
+    const double var = n_samp > 1 ? fmax(q / N - mean * mean, 0.0) * N / (N - 1.0) : 0.0;
     const double D = disc[obs_row[o]];
     price[o] = D * mean;
     se[o] = D * sqrt(var / N);
@@ -161,15 +174,19 @@ __global__ void __launch_bounds__(256) mc_cliquet_kernel(CliqDesc d, const int32
     for (int64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
         const int64_t path = tile * 256 + threadIdx.x;
         const bool active = path < d.n_paths;
+        const bool anti = d.anti != 0;
+        const R sg = path_sign<R>(path, anti);
         R X = 0, A = A0, Fp = 0, sum = 0;
         int next = 0;
         uint4 w = make_uint4(0, 0, 0, 0);
         for (int s = 0; s < d.m_max; ++s) {
-            if ((s & 1) == 0) w = philox4x32_10(make_uint4((uint32_t)path, (uint32_t)(s >> 1), 0u, 2u), d.key0, d.key1);
+            if ((s & 1) == 0) w = path_words(path, (uint32_t)(s >> 1), anti, d.key0, d.key1);
             const R u1 = MC<R>::unit((s & 1) ? w.z : w.x);
             const R u2 = MC<R>::unit((s & 1) ? w.w : w.y);
             R z1, z2;
             MC<R>::normals(u1, u2, z1, z2);
+            z1 *= sg;
+            z2 *= sg;
             const StepC<R> c = st[s];
             const R vh = MC<R>::exp2_(fma(bm1, fmax(X, xabs), A));
             A = fma(c.nz, z1, A + c.nd);
@@ -188,6 +205,10 @@ __global__ void __launch_bounds__(256) mc_cliquet_kernel(CliqDesc d, const int32
         }
         const double v = active ? (double)fmax(gf, fmin(gc, sum)) : 0.0;
         double vs = v, vq = v * v;
+        if (anti) {   // one squared sample per antithetic pair (neighbouring lanes), on the even lane
+            const double pm = 0.5 * (v + __shfl_xor(v, 1, 64));
+            vq = (lane & 1) ? 0.0 : pm * pm;
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             vs += __shfl_xor(vs, off, 64);

@@ -364,6 +364,10 @@ int check_mc(sabr_ctx *c, const sabr_mc *m) {
     if (!m) return fail(c, SABR_E_INVAL, "mc settings are NULL");
     if (m->n_paths < 1 || m->n_paths > (int64_t)0xffffffffLL) return fail(c, SABR_E_INVAL, "n_paths must be in [1, 2^32)");
     if (m->steps_per_year < 1) return fail(c, SABR_E_INVAL, "steps_per_year must be >= 1");
+    if (m->scheme != SABR_MC_PLAIN && m->scheme != SABR_MC_ANTITHETIC)
+        return fail(c, SABR_E_INVAL, "unknown path scheme %d", m->scheme);
+    if (m->scheme == SABR_MC_ANTITHETIC && m->n_paths % 2 != 0)
+        return fail(c, SABR_E_INVAL, "antithetic paths come in pairs: n_paths must be even");
     return SABR_OK;
 }
 
@@ -912,6 +916,7 @@ int mc_objective_device(sabr_ctx *c, const McGrid &g, int model, int n_par, int 
     d.key0 = (uint32_t)(mc.seed & 0xffffffffu);
     d.key1 = (uint32_t)(mc.seed >> 32);
     d.model = model;
+    d.anti = mc.scheme == SABR_MC_ANTITHETIC;
     d.t_max = g.t_max;
     const bool direct = crn_direct(c, n_x, mc.n_paths, g.n_obs);
     crn_geometry(n_x, mc.n_paths, d, direct);
@@ -1429,6 +1434,7 @@ int sabr_mc_price(sabr_ctx *c, const sabr_market *market, const sabr_problem *pr
     for (int k = 0; k < base_npar(problem->model); ++k) d.x[k] = problem->x0[k];
     d.key0 = (uint32_t)(mc->seed & 0xffffffffu);
     d.key1 = (uint32_t)(mc->seed >> 32);
+    d.anti = mc->scheme == SABR_MC_ANTITHETIC;
     const bool fp32 = precision == SABR_FP32;
     const int64_t tiles = (mc->n_paths + 255) / 256;
     const int n_blocks = (int)std::min<int64_t>(tiles, 2048);
@@ -1449,7 +1455,8 @@ int sabr_mc_price(sabr_ctx *c, const sabr_market *market, const sabr_problem *pr
     const int32_t *orow = g.obsrow;
     const double *disc = g.disc;
     int nblk = n_blocks;
-    void *a2[] = {&n_obs, &nblk, &np, &ps, &pq, &orow, &disc, &pr, &se};
+    int anti = d.anti;
+    void *a2[] = {&n_obs, &nblk, &np, &anti, &ps, &pq, &orow, &disc, &pr, &se};
     if ((rc = launch(c, false, "mc_price_finalize", mc_price_finalize_ptr(), dim3((n_obs + 255) / 256), dim3(256), a2, 0)))
         return rc;
     HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
@@ -1521,6 +1528,7 @@ int sabr_mc_price_noalloc(sabr_ctx *c, const sabr_market *market, const sabr_pro
     for (int k = 0; k < base_npar(problem->model); ++k) d.x[k] = problem->x0[k];
     d.key0 = (uint32_t)(mc->seed & 0xffffffffu);
     d.key1 = (uint32_t)(mc->seed >> 32);
+    d.anti = mc->scheme == SABR_MC_ANTITHETIC;
     const bool fp32 = precision == SABR_FP32;
     const void *fn = mc_price_kernel_ptr(fp32);
     const size_t smem = mc_price_smem_bytes(fp32, m_max, n_obs);
@@ -1529,7 +1537,8 @@ int sabr_mc_price_noalloc(sabr_ctx *c, const sabr_market *market, const sabr_pro
     if ((rc = launch(c, false, "mc_price_kernel", fn, dim3(n_blocks), dim3(256), a1, smem))) return rc;
     int no = n_obs, nblk = n_blocks;
     int64_t np = mc->n_paths;
-    void *a2[] = {&no, &nblk, &np, &ps, &pq, &orow, &disc, &pr, &se};
+    int anti = d.anti;
+    void *a2[] = {&no, &nblk, &np, &anti, &ps, &pq, &orow, &disc, &pr, &se};
     if ((rc = launch(c, false, "mc_price_finalize", mc_price_finalize_ptr(), dim3((n_obs + 255) / 256), dim3(256), a2, 0)))
         return rc;
     HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double) * n_obs, hipMemcpyDeviceToHost, c->stream));
@@ -1624,6 +1633,7 @@ int sabr_mc_cliquet(sabr_ctx *c, const sabr_problem *problem, double f0, double 
     d.global_cap = global_cap;
     d.key0 = (uint32_t)(mc->seed & 0xffffffffu);
     d.key1 = (uint32_t)(mc->seed >> 32);
+    d.anti = mc->scheme == SABR_MC_ANTITHETIC;
     const bool fp32 = precision == SABR_FP32;
     const int64_t tiles = (mc->n_paths + 255) / 256;
     const int n_blocks = (int)std::min<int64_t>(tiles, 2048);
@@ -1644,7 +1654,8 @@ int sabr_mc_cliquet(sabr_ctx *c, const sabr_problem *problem, double f0, double 
     if ((rc = launch(c, true, "mc_cliquet_kernel", fn, dim3(n_blocks), dim3(256), a1, smem))) return rc;
     int one = 1, nblk = n_blocks;
     int64_t np = mc->n_paths;
-    void *a2[] = {&one, &nblk, &np, &ps, &pq, &drow, &ddisc, &pr, &se};
+    int anti = d.anti;
+    void *a2[] = {&one, &nblk, &np, &anti, &ps, &pq, &drow, &ddisc, &pr, &se};
     if ((rc = launch(c, false, "mc_price_finalize", mc_price_finalize_ptr(), dim3(1), dim3(64), a2, 0))) return rc;
     HIPCHK(c, hipMemcpyAsync(price, pr, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     if (std_err) HIPCHK(c, hipMemcpyAsync(std_err, se, sizeof(double), hipMemcpyDeviceToHost, c->stream));

@@ -15,6 +15,7 @@ struct McDesc {
     double dt, f0, beta;
     double x[kMaxPar];
     uint32_t key0, key1;
+    int32_t anti, pad;   // antithetic path pairs
 };
 
 // Common-random-number Monte Carlo of many parameter sets (lane = set).
@@ -24,7 +25,7 @@ struct McCrnDesc {
     int32_t np_stride, beta_free;
     double dt, f0, beta;
     uint32_t key0, key1;
-    int32_t model, pad;
+    int32_t model, anti;   // anti: antithetic path pairs
     double t_max;
 };
 
@@ -51,7 +52,7 @@ struct AtmDesc {
 
 // Cliquet on the Monte Carlo paths of one parameter set (lane = path).
 struct CliqDesc {
-    int32_t model, n_reset, m_max, pad;
+    int32_t model, n_reset, m_max, anti;   // anti: antithetic path pairs
     int64_t n_paths;
     double dt, f0, beta;
     double x[kMaxPar];

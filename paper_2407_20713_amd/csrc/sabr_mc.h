@@ -32,6 +32,18 @@ template <> struct MC<double> {
     static __device__ __forceinline__ double unit(uint32_t w) { return unit_u24d(w); }
 };
 
+// Philox words of step pair `step2` of a path under the path scheme: plain
+// (counter (path, step2, 0, 2)), or antithetic pairs, in which paths 2k and
+// 2k + 1 both draw counter (k, step2, 0, 2) and the odd path negates the
+// normals (path_sign).
+__device__ __forceinline__ uint4 path_words(int64_t path, uint32_t step2, bool anti, uint32_t k0, uint32_t k1) {
+    return philox4x32_10(make_uint4((uint32_t)(anti ? (path >> 1) : path), step2, 0u, 2u), k0, k1);
+}
+template <typename R>
+__device__ __forceinline__ R path_sign(int64_t path, bool anti) {
+    return (anti && (path & 1)) ? (R)-1 : (R)1;
+}
+
 // Functional parameters of the three models at time t (eqs. "el_fun_1",
 // "el_fun_3"); the static model has constant nu, rho.
 template <typename R>
@@ -176,11 +188,16 @@ __device__ inline void crn_block(const McCrnDesc &d, int tile, int pb, const dou
         int mi = 0;
         int mnext = mat_steps[0];
         for (int s0 = 0; s0 < d.m_max; s0 += CH) {
-            const uint4 w = philox4x32_10(make_uint4((uint32_t)(path + q_self), (uint32_t)((s0 >> 1) + j_self), 0u, 2u),
-                                          d.key0, d.key1);
+            const uint4 w = path_words(path + q_self, (uint32_t)((s0 >> 1) + j_self), d.anti != 0, d.key0, d.key1);
             float ze1, ze2, zo1, zo2;
             MC<float>::normals(unit_u24f(w.x), unit_u24f(w.y), ze1, ze2);
             MC<float>::normals(unit_u24f(w.z), unit_u24f(w.w), zo1, zo2);
+            if (d.anti && ((path + q_self) & 1)) {
+                ze1 = -ze1;
+                ze2 = -ze2;
+                zo1 = -zo1;
+                zo2 = -zo2;
+            }
             if constexpr (LDSB) {
                 __syncthreads();
                 ztab[(2 * j_self) * NPATH + q_self] = make_float2(ze1, ze2);

@@ -704,6 +704,8 @@ int sabr_server_submit(sabr_server *s, const sabr_market *market, const sabr_pro
     if (q.sa.n_chains > cap) return fail(s->ctx, SABR_E_INVAL, "at most %d chains per request of this kind", cap);
     if (n_pts > kSlotMaxPts || q.market.n_mat > kSlotMaxMat || (kind == KIND_MC && n_pts > kSlotMaxMcObs))
         return fail(s->ctx, SABR_E_INVAL, "grid too large for a serving slot");
+    if (kind == KIND_MC && q.mc.scheme != SABR_MC_PLAIN)
+        return fail(s->ctx, SABR_E_INVAL, "the serving loop takes the plain path scheme only");
     // each lane of a path block adds its block's payoffs in float: at most
     // 256 per block (the bound of the float partial sums), kMcPBlocks blocks
     if (kind == KIND_MC && q.mc.n_paths > (int64_t)256 * kMcPBlocks)

@@ -21,6 +21,7 @@ SABR_E_DEVICE, SABR_E_INFEASIBLE, SABR_E_TIMEOUT, SABR_E_CANCELLED = -4, -5, -6,
 SABR_STATIC, SABR_DYN_I, SABR_DYN_II = 0, 1, 2
 SABR_F_HAGAN, SABR_F_OBLOJ, SABR_F_EXPANSION = 0, 1, 2
 SABR_OBJ_FORMULA, SABR_OBJ_MC = 0, 1
+SABR_MC_PLAIN, SABR_MC_ANTITHETIC = 0, 1
 SABR_W_ABSOLUTE, SABR_W_RELATIVE = 0, 1
 SABR_FP64, SABR_FP32 = 0, 1
 
@@ -58,7 +59,7 @@ class sabr_sa(C.Structure):
 
 
 class sabr_mc(C.Structure):
-    _fields_ = [("n_paths", C.c_int64), ("steps_per_year", C.c_int32), ("seed", C.c_uint64)]
+    _fields_ = [("n_paths", C.c_int64), ("steps_per_year", C.c_int32), ("scheme", C.c_int32), ("seed", C.c_uint64)]
 
 
 class sabr_result(C.Structure):
@@ -263,13 +264,13 @@ class Request:
 
     def __init__(self, market, problem, kind=SABR_OBJ_FORMULA, formula=SABR_F_HAGAN, weighting=SABR_W_ABSOLUTE,
                  precision=SABR_FP64, n_chains=64, n_iters=1000, chain_len=10, T0=0.0, cooling=None, step0=0.1,
-                 step_min=1e-4, seed=1, polish=False, n_paths=0, steps_per_year=250, mc_seed=0):
+                 step_min=1e-4, seed=1, polish=False, n_paths=0, steps_per_year=250, mc_seed=0, mc_scheme=0):
         self.market, self.problem = market, problem
         if cooling is None:
             cooling = 0.99 ** (1000.0 / n_iters)
         self.obj = sabr_objspec(kind, formula, weighting, precision)
         self.sa = sabr_sa(n_chains, n_iters, chain_len, T0, cooling, step0, step_min, seed, int(polish))
-        self.mc = sabr_mc(n_paths, steps_per_year, mc_seed)
+        self.mc = sabr_mc(n_paths=n_paths, steps_per_year=steps_per_year, scheme=mc_scheme, seed=mc_seed)
 
     def c(self):
         return sabr_request(self.market.c(), self.problem.c(), self.obj, self.sa, self.mc)
@@ -363,7 +364,7 @@ def _ptr(a):
 
 def sabr_objective_batch(ctx, market, problem, X, kind=SABR_OBJ_FORMULA, formula=SABR_F_HAGAN,
                          weighting=SABR_W_ABSOLUTE, precision=SABR_FP64, n_paths=0, steps_per_year=250,
-                         mc_seed=0, f=None, model=None, want_model=False):
+                         mc_seed=0, f=None, model=None, want_model=False, mc_scheme=0):
     """Objective at every row of X (numpy or torch, host or device).  Returns (f, model)."""
     is_torch = hasattr(X, "data_ptr")
     if not is_torch:
@@ -378,7 +379,7 @@ def sabr_objective_batch(ctx, market, problem, X, kind=SABR_OBJ_FORMULA, formula
         model = np.zeros((n_x, market.n_obs)) if not is_torch else X.new_zeros((n_x, market.n_obs))
     m, p = market.c(), problem.c()
     o = sabr_objspec(kind, formula, weighting, precision)
-    mc = sabr_mc(n_paths, steps_per_year, mc_seed)
+    mc = sabr_mc(n_paths=n_paths, steps_per_year=steps_per_year, scheme=mc_scheme, seed=mc_seed)
     if is_torch:
         torch.cuda.synchronize()      # outputs allocated on torch's stream exist before the library writes
     ctx.check(lib().sabr_objective_batch(ctx.h, C.byref(m), C.byref(p), C.byref(o), C.byref(mc), n_x,
@@ -386,22 +387,23 @@ def sabr_objective_batch(ctx, market, problem, X, kind=SABR_OBJ_FORMULA, formula
     return f, model
 
 
-def sabr_mc_price(ctx, market, problem, n_paths, steps_per_year=250, seed=0, precision=SABR_FP32):
+def sabr_mc_price(ctx, market, problem, n_paths, steps_per_year=250, seed=0, precision=SABR_FP32, scheme=0):
     """Monte Carlo call prices at problem.x0; returns (price, std_err)."""
     price = np.zeros(market.n_obs)
     se = np.zeros(market.n_obs)
     m, p = market.c(), problem.c()
-    mc = sabr_mc(n_paths, steps_per_year, seed)
+    mc = sabr_mc(n_paths=n_paths, steps_per_year=steps_per_year, scheme=scheme, seed=seed)
     ctx.check(lib().sabr_mc_price(ctx.h, C.byref(m), C.byref(p), C.byref(mc), precision, _dp(price), _dp(se)))
     return price, se
 
 
-def sabr_mc_price_noalloc(ctx, market, problem, n_paths, steps_per_year=250, seed=0, precision=SABR_FP32):
+def sabr_mc_price_noalloc(ctx, market, problem, n_paths, steps_per_year=250, seed=0, precision=SABR_FP32,
+                          scheme=0):
     """sabr_mc_price on the library's static device scratch (no device allocation)."""
     price = np.zeros(market.n_obs)
     se = np.zeros(market.n_obs)
     m, p = market.c(), problem.c()
-    mc = sabr_mc(n_paths, steps_per_year, seed)
+    mc = sabr_mc(n_paths=n_paths, steps_per_year=steps_per_year, scheme=scheme, seed=seed)
     ctx.check(lib().sabr_mc_price_noalloc(ctx.h, C.byref(m), C.byref(p), C.byref(mc), precision, _dp(price),
                                           _dp(se)))
     return price, se
@@ -416,12 +418,12 @@ def sabr_atm_seed(ctx, market, problem):
 
 
 def sabr_mc_cliquet(ctx, problem, f0, reset_T, local_floor, local_cap, global_floor, global_cap, n_paths,
-                    steps_per_year=250, seed=0, disc=1.0, precision=SABR_FP32):
+                    steps_per_year=250, seed=0, disc=1.0, precision=SABR_FP32, scheme=0):
     """Cliquet price at problem.x0 on the Monte Carlo paths; returns (price, std_err)."""
     rt = _f64(reset_T)
     price, se = C.c_double(), C.c_double()
     p = problem.c()
-    mc = sabr_mc(n_paths, steps_per_year, seed)
+    mc = sabr_mc(n_paths=n_paths, steps_per_year=steps_per_year, scheme=scheme, seed=seed)
     ctx.check(lib().sabr_mc_cliquet(ctx.h, C.byref(p), f0, disc, len(rt), _dp(rt), local_floor, local_cap,
                                     global_floor, global_cap, C.byref(mc), precision, C.byref(price),
                                     C.byref(se)))

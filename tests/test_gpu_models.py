@@ -12,6 +12,8 @@ Tolerances:
                                count, x within 1e-12);
   Monte Carlo prices, FP32   : 5e-5 relative on identical normals (+1e-7 abs);
   cliquet, FP32 / FP64       : 1e-4 / 1e-9 relative on identical normals;
+  antithetic standard errors : FP64 1e-6 relative, FP32 2e-3 relative (pair means
+                               of float payoffs);
   at-the-money start point   : 1e-13 relative (device log/pow against glibc).
 """
 import math
@@ -387,3 +389,127 @@ def test_fp32_objective_at_zero_nu_matches_oracle(S, ctx, oracle):
         say("nu", X[i][2], f0[i], f1[i], ref_f)
         assert np.isfinite(f0[i]) and abs(f0[i] - ref_f) <= tol and abs(f1[i] - ref_f) <= tol
         assert np.max(np.abs(mod[i] - ref_v)) < 2e-5
+
+
+# Antithetic path pairs (a variance reduction the paper does not use): the
+# same parity bars as the plain scheme, on the oracle's pairs.
+ANTI_CASES = [
+    (inputs.STATIC, [0.3, -0.5, 0.8], 0.7),
+    (inputs.DYN_I, [0.393329, -1.0, 0.941565, 0.001, 1.246906], 1.0),
+    (inputs.DYN_II, [0.398436, -0.964678, 1.285129, 0.0, 2.059560, 0.101632, -0.086294, 0.0, 1.302296], 0.999579),
+]
+
+
+@pytest.mark.parametrize("model,x,beta", ANTI_CASES)
+@pytest.mark.parametrize("prec", [1, 0])
+def test_mc_price_antithetic_matches_oracle(S, ctx, oracle, model, x, beta, prec):
+    """European calls on 3000 paths (1500 pairs; a ragged last tile) under the
+    antithetic scheme: prices and pair-based standard errors equal the
+    oracle's on the same pairs of normals; the entry point without
+    allocation gives the same bits."""
+    say("mc antithetic", model, prec)
+    g = inputs.make_grid([0.25, 0.5, 1.0], [np.exp(np.linspace(-0.3, 0.3, 5))] * 3, f0=1.0,
+                         disc=[0.99, 0.98, 0.96])
+    m = omkt(oracle, g)
+    ref, rse = oracle.mc_prices(m, model, x, beta, 3000, 250, 0xA17, scheme=oracle.MC_ANTITHETIC)
+    mk, pb = S.Market.from_grid(g), S.Problem(model, beta, x0=x)
+    got, gse = S.sabr_mc_price(ctx, mk, pb, 3000, 250, 0xA17, precision=prec, scheme=S.SABR_MC_ANTITHETIC)
+    if prec == S.SABR_FP32:
+        np.testing.assert_allclose(got, ref, rtol=5e-5, atol=1e-7)
+        np.testing.assert_allclose(gse, rse, rtol=2e-3, atol=1e-8)
+    else:
+        np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-13)
+        np.testing.assert_allclose(gse, rse, rtol=1e-6)
+    na, nse = S.sabr_mc_price_noalloc(ctx, mk, pb, 3000, 250, 0xA17, precision=prec, scheme=S.SABR_MC_ANTITHETIC)
+    assert np.array_equal(na, got) and np.array_equal(nse, gse)
+    # the pairs differ from the plain paths: the plain estimate is another one
+    plain, _ = S.sabr_mc_price(ctx, mk, pb, 3000, 250, 0xA17, precision=prec)
+    assert not np.array_equal(plain, got)
+
+
+@pytest.mark.parametrize("model", [inputs.STATIC, inputs.DYN_I])
+def test_mc_objective_antithetic_matches_oracle(S, ctx, oracle, model):
+    """Monte Carlo objective of 70 parameter vectors on common antithetic
+    pairs (1500 paths): model prices and relative-error objective equal the
+    oracle's on the same pairs."""
+    g = inputs.make_grid([0.25, 0.75], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0, disc=[0.995, 0.985])
+    m = omkt(oracle, g)
+    xt = [0.2, -0.3, 0.5] if model == inputs.STATIC else [0.2, -0.3, 0.5, 0.4, 0.6]
+    tgt, _ = oracle.mc_prices(m, model, xt, 0.7, 1500, 250, 98, scheme=oracle.MC_ANTITHETIC)
+    m.target = tgt
+    lb, ub = inputs.box(model)
+    rng = np.random.default_rng(52)
+    X = lb + (ub - lb) * (0.2 + 0.6 * rng.random((70, len(lb))))
+    f, mod = S.sabr_objective_batch(ctx, S.Market.from_grid(g, target=tgt), S.Problem(model, 0.7), X,
+                                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32,
+                                    n_paths=1500, steps_per_year=250, mc_seed=98, want_model=True,
+                                    mc_scheme=S.SABR_MC_ANTITHETIC)
+    for i in range(0, len(X), 7):
+        ref, _ = oracle.mc_prices(m, model, X[i], 0.7, 1500, 250, 98, scheme=oracle.MC_ANTITHETIC)
+        np.testing.assert_allclose(mod[i], ref, rtol=5e-5, atol=1e-7)
+        rf = oracle.objective_mc(m, model, X[i], 0.7, 1500, 250, 98, scheme=oracle.MC_ANTITHETIC)
+        assert abs(f[i] - rf) <= 1e-3 * rf + 1e-8
+
+
+def test_mc_calibration_antithetic_follows_oracle(S, ctx, oracle):
+    """Technique II on antithetic pairs: a tiny Monte Carlo calibration (8
+    chains x 20 iterations, 512 paths) takes the oracle's accept decisions on
+    the same pairs (objectives agree to ~1e-6 relative)."""
+    g = inputs.make_grid([0.25, 0.5], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0)
+    m = omkt(oracle, g)
+    xt = [0.2, -0.3, 0.5]
+    tgt, _ = oracle.mc_prices(m, inputs.STATIC, xt, 0.7, 512, 250, 4243, scheme=oracle.MC_ANTITHETIC)
+    m.target = tgt
+    lb, ub = inputs.box(inputs.STATIC)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub), kind=S.SABR_OBJ_MC,
+                    weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=8, n_iters=20, seed=3,
+                    n_paths=512, steps_per_year=250, mc_seed=4243, mc_scheme=S.SABR_MC_ANTITHETIC)
+    got = S.sabr_calibrate(ctx, req)
+    ref = oracle.calibrate(m, inputs.STATIC, lb, ub, 0.7, 8, 20, 3, objective=oracle.OBJ_MC,
+                           weighting=oracle.RELATIVE, mc_paths=512, mc_steps_per_year=250, mc_seed=4243,
+                           mc_scheme=oracle.MC_ANTITHETIC)
+    say("mc anti calibration", got["x"], got["n_accept"], ref["x"], ref["n_accept"])
+    assert got["n_accept"] == ref["n_accept"]
+    np.testing.assert_allclose(got["x"], ref["x"], atol=1e-12)
+    assert abs(got["f"] - ref["f"]) <= 1e-3 * ref["f"]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_cliquet_antithetic_matches_oracle(S, ctx, oracle, prec):
+    """The paper's cliquet on 3000 antithetic paths: price and pair-based
+    standard error equal the oracle's on the same pairs."""
+    kw = dict(CLIQUET)
+    model, x, beta = ANTI_CASES[1]
+    ref, rse = oracle.mc_cliquet(model, x, beta, 1.3, kw["reset_T"], kw["local_floor"], kw["local_cap"],
+                                 kw["global_floor"], kw["global_cap"], 3000, 250, 0xC12, disc=0.97,
+                                 scheme=oracle.MC_ANTITHETIC)
+    got, gse = S.sabr_mc_cliquet(ctx, S.Problem(model, beta, x0=x), 1.3, kw["reset_T"], kw["local_floor"],
+                                 kw["local_cap"], kw["global_floor"], kw["global_cap"], 3000, 250, 0xC12,
+                                 disc=0.97, precision=prec, scheme=S.SABR_MC_ANTITHETIC)
+    if prec == S.SABR_FP32:
+        assert got == pytest.approx(ref, rel=1e-4)
+    else:
+        assert got == pytest.approx(ref, rel=1e-9)
+        assert gse == pytest.approx(rse, rel=1e-6)
+
+
+def test_antithetic_validation(S, ctx):
+    """An odd path count or an unknown scheme is refused; the serving loop
+    takes the plain scheme only."""
+    g = inputs.make_grid([0.5], [np.exp(np.linspace(-0.2, 0.2, 4))], f0=1.0)
+    mk, pb = S.Market.from_grid(g), S.Problem(S.SABR_STATIC, 0.7, x0=[0.2, -0.3, 0.5])
+    for n, sch in ((1001, S.SABR_MC_ANTITHETIC), (1000, 2)):
+        with pytest.raises(S.SabrError) as e:
+            S.sabr_mc_price(ctx, mk, pb, n, 250, 1, scheme=sch)
+        assert e.value.code == S.SABR_E_INVAL
+    lb, ub = inputs.box(inputs.STATIC)
+    srv = S.Server(ctx, max_slots=4)
+    try:
+        req = S.Request(S.Market.from_grid(g, target=np.full(4, 0.05)), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                        kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=16,
+                        n_iters=10, n_paths=1024, mc_scheme=S.SABR_MC_ANTITHETIC)
+        with pytest.raises(S.SabrError) as e:
+            srv.submit(req)
+        assert e.value.code == S.SABR_E_INVAL and "plain" in str(e.value)
+    finally:
+        srv.close()

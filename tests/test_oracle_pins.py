@@ -521,6 +521,57 @@ def test_mc_short_maturity_matches_hagan(oracle):
         assert abs(p[j] - ref) < 3.5 * se[j] + 1e-4
 
 
+def test_mc_antithetic_pairs_brute_force(oracle):
+    """Antithetic scheme on four paths of geometric Brownian motion (beta = 1,
+    nu = 0, so each log-Euler step is exact): paths 0 and 2 take the plain
+    normals of counters 0 and 1, paths 1 and 3 the same normals negated; the
+    price is the discounted mean of the four payoffs and the standard error
+    that of the two pair means, |m1 - m0| / 2 times the discount."""
+    T, f, D, sig, rho = 0.1, 1.0, 0.95, 0.3, -0.4
+    Ks = [0.9, 1.0, 1.2]
+    m = _one(oracle, T, f, Ks, disc=D)
+    M = 25                                  # floor(0.1 * 250)
+    dt = 1.0 / 250
+    pays = []
+    for k in range(2):
+        for sgn in (1.0, -1.0):
+            F = f
+            for i in range(M):
+                z1, z2 = oracle.mc_normals(13, k, i)
+                w = sgn * (rho * z1 + math.sqrt(1 - rho * rho) * z2)
+                F *= math.exp(sig * w * math.sqrt(dt) - sig * sig * dt / 2)
+            pays.append([max(F - K, 0.0) for K in Ks])
+    pays = np.array(pays)
+    p, se = oracle.mc_prices(m, oracle.STATIC, [sig, rho, 0.0], 1.0, 4, 250, 13, scheme=oracle.MC_ANTITHETIC)
+    np.testing.assert_allclose(p, D * pays.mean(axis=0), rtol=1e-12, atol=1e-15)
+    pair = 0.5 * (pays[0::2] + pays[1::2])
+    np.testing.assert_allclose(se, D * np.abs(pair[1] - pair[0]) / 2, rtol=1e-10, atol=1e-15)
+    # the odd path of a pair negates both normals of its even partner
+    for step in (0, 1, 7):
+        a = oracle.path_normals(13, oracle.MC_ANTITHETIC, 6, step)
+        b = oracle.path_normals(13, oracle.MC_ANTITHETIC, 7, step)
+        assert a == oracle.mc_normals(13, 3, step) and b == (-a[0], -a[1])
+
+
+def test_mc_antithetic_is_black_with_smaller_error(oracle):
+    """beta = 1, nu = 0: the antithetic estimate is Black's price within its
+    error, and for these monotone payoffs the pair means vary less than the
+    paths (negatively correlated halves): a smaller standard error than the
+    plain scheme's on as many paths."""
+    T, f = 0.25, 1.0
+    Ks = [0.8, 1.0, 1.25]
+    m = _one(oracle, T, f, Ks)
+    x = [0.3, -0.5, 0.0]
+    p, se = oracle.mc_prices(m, oracle.STATIC, x, 1.0, 1 << 15, 250, 7, scheme=oracle.MC_ANTITHETIC)
+    _, se_plain = oracle.mc_prices(m, oracle.STATIC, x, 1.0, 1 << 15, 250, 7)
+    Teff = 62 / 250
+    for j, K in enumerate(Ks):
+        assert abs(p[j] - oracle.black_call(f, K, Teff, 0.3, 1.0)) < 3.5 * se[j]
+        assert se[j] < se_plain[j]
+    with pytest.raises(ValueError):
+        oracle.mc_prices(m, oracle.STATIC, x, 1.0, 1001, 250, 7, scheme=oracle.MC_ANTITHETIC)
+
+
 def test_mc_dynamic_zero_rates_is_static_bitwise(oracle):
     """Case I with a = b = 0 follows the static paths bit for bit."""
     m = _one(oracle, 0.5, 1.0, [0.9, 1.1])
@@ -572,6 +623,20 @@ def test_cliquet_lognormal_closed_form(oracle):
     sig, Fl, Cl, D = 0.25, -0.02, 0.02, 0.97
     p, se = oracle.mc_cliquet(oracle.STATIC, [sig, 0.3, 0.0], 1.0, 1.3, RESETS, Fl, Cl, -1e9, 1e9, 1 << 15, 250, 19,
                               disc=D)
+    steps = [62, 125, 187, 250]
+    ref = 0.0
+    for i in range(1, 4):
+        var = sig * sig * (steps[i] - steps[i - 1]) / 250.0
+        ref += Fl + _black_unit(1.0 + Fl, var) - _black_unit(1.0 + Cl, var)
+    assert abs(p - D * ref) < 3.5 * se, (p, D * ref, se)
+
+
+def test_cliquet_antithetic_lognormal_closed_form(oracle):
+    """The cliquet closed form above holds for the antithetic estimate too,
+    within its error (pairs of paths with negated normals)."""
+    sig, Fl, Cl, D = 0.25, -0.02, 0.02, 0.97
+    p, se = oracle.mc_cliquet(oracle.STATIC, [sig, 0.3, 0.0], 1.0, 1.3, RESETS, Fl, Cl, -1e9, 1e9, 1 << 15, 250, 19,
+                              disc=D, scheme=oracle.MC_ANTITHETIC)
     steps = [62, 125, 187, 250]
     ref = 0.0
     for i in range(1, 4):
