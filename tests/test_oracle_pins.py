@@ -526,7 +526,8 @@ def test_mc_antithetic_pairs_brute_force(oracle):
     nu = 0, so each log-Euler step is exact): paths 0 and 2 take the plain
     normals of counters 0 and 1, paths 1 and 3 the same normals negated; the
     price is the discounted mean of the four payoffs and the standard error
-    that of the two pair means, |m1 - m0| / 2 times the discount."""
+    that of the two pair means, |m1 - m0| / 2 times the discount; the plain
+    scheme on two paths takes the even ones, with the sample standard error."""
     T, f, D, sig, rho = 0.1, 1.0, 0.95, 0.3, -0.4
     Ks = [0.9, 1.0, 1.2]
     m = _one(oracle, T, f, Ks, disc=D)
@@ -546,6 +547,11 @@ def test_mc_antithetic_pairs_brute_force(oracle):
     np.testing.assert_allclose(p, D * pays.mean(axis=0), rtol=1e-12, atol=1e-15)
     pair = 0.5 * (pays[0::2] + pays[1::2])
     np.testing.assert_allclose(se, D * np.abs(pair[1] - pair[0]) / 2, rtol=1e-10, atol=1e-15)
+    # the plain scheme on two paths: their mean and sample standard error
+    p3, se3 = oracle.mc_prices(m, oracle.STATIC, [sig, rho, 0.0], 1.0, 2, 250, 13)
+    plain = np.array([pays[0], pays[2]])      # plain paths 0 and 1 are the even antithetic paths
+    np.testing.assert_allclose(p3, D * plain.mean(axis=0), rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(se3, D * plain.std(axis=0, ddof=1) / math.sqrt(2), rtol=1e-10, atol=1e-15)
     # the odd path of a pair negates both normals of its even partner
     for step in (0, 1, 7):
         a = oracle.path_normals(13, oracle.MC_ANTITHETIC, 6, step)
