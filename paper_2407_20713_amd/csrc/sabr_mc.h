@@ -272,9 +272,20 @@ __device__ inline void crn_price_tile(const McCrnDesc &d, int tile, int o, const
                                       double *e2, int64_t e2_stride, double *s_sum) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const float *p = part + (((size_t)tile * d.n_obs + o) * d.n_pblocks) * 64 + lane;
-    double sm = 0.0;
-    for (int b = w; b < d.n_pblocks; b += nw) sm += (double)p[(size_t)b * 64];
-    s_sum[threadIdx.x] = sm;
+    // four blocks' partials read together into four sums (four loads in
+    // flight per wave), then the rest
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int b = w;
+    for (; b + 3 * nw < d.n_pblocks; b += 4 * nw) {
+        const float v0 = p[(size_t)b * 64], v1 = p[(size_t)(b + nw) * 64];
+        const float v2 = p[(size_t)(b + 2 * nw) * 64], v3 = p[(size_t)(b + 3 * nw) * 64];
+        s0 += (double)v0;
+        s1 += (double)v1;
+        s2 += (double)v2;
+        s3 += (double)v3;
+    }
+    for (; b < d.n_pblocks; b += nw) s0 += (double)p[(size_t)b * 64];
+    s_sum[threadIdx.x] = (s0 + s1) + (s2 + s3);
     __syncthreads();
     const int64_t chain = (int64_t)tile * 64 + lane;
     if (w == 0 && chain < d.n_chains) {
