@@ -232,7 +232,12 @@ def fp32_vs_oracle(S, ctx, reqs, results):
 
 
 # --- other workloads (not the default line) ------------------------------------
-def roofline(flops, kernel_s, kernel, launches, counters=None):
+def roofline(flops, kernel_s, kernel, launches, counters=None, units=None):
+    """The dominant kernel against the FP32 vector peak: algorithmic flops of
+    a launch over its average time; beside it, from the counter summary of
+    the same kernel sources, the HBM traffic, the VALU issue rate and the FP32
+    flops the hardware counted per unit of work (FMA = 2, every lane), scaled
+    to this launch's `units`."""
     d = {"bound": "alu", "achieved": flops / kernel_s / 1e12, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
          "frac": flops / kernel_s / 1e12 / PEAK_FP32_TFLOPS, "traffic": None, "kernel": kernel,
          "avg_kernel_ms": kernel_s * 1e3, "launches": launches}
@@ -240,6 +245,10 @@ def roofline(flops, kernel_s, kernel, launches, counters=None):
         d["traffic"] = counters.get("traffic_bytes_per_launch")
         d["valu_insts_per_simd_cycle"] = counters.get("valu_insts_per_simd_cycle")
         d["valu_busy_rocprof"] = counters.get("valu_busy_rocprof")
+        per_unit = counters.get("executed_fp32_flops_per_unit")
+        if per_unit is not None and units:
+            d["executed_fp32_tflops"] = per_unit * units / kernel_s / 1e12
+            d["executed_fp32_frac"] = d["executed_fp32_tflops"] / PEAK_FP32_TFLOPS
         d["counters_from"] = counters.get("file")
     return d
 
@@ -287,7 +296,8 @@ def bench_mc_calibration(S, inputs, ctx, args):
                                    "paths x 500 steps, FP32 paths" % iters},
             "roofline": roofline(1024 * 65536 * m_max * FLOP_MC_STEP, k_s, name, n,
                                  counter_summary("counters_mc_crn_kernel_mc_calibration.md",
-                                                 ["sabr_dev.h", "sabr_mc.h", "kernels_mc.hip"])),
+                                                 ["sabr_dev.h", "sabr_mc.h", "kernels_mc.hip"]),
+                                 units=1024 * 65536 * m_max),
             "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"],
             "self_consistent": {"param_error_vs_truth": float(np.max(np.abs(res_same["x"] - xt))),
                                 "f": res_same["f"], "wall_s": wall2,
@@ -323,7 +333,7 @@ def bench_dynamic(S, inputs, ctx, args):
             "config": {"workload": "dynamic SABR case I, 20 x 20 joint fit, 8192 chains x %d iterations, FP32 "
                                    "bulk, FP64 polish" % iters},
             "roofline": roofline(flops, k_s, name, n,
-                                 counter_summary("sa_kernel_dynamic_case1.md", SA_SOURCES)),
+                                 counter_summary("sa_kernel_dynamic_case1.md", SA_SOURCES), units=8192 * iters),
             "param_error_vs_truth": float(np.max(np.abs(res["x"] - xt))), "f": res["f"]}
 
 
@@ -531,7 +541,7 @@ def main():
     param_err, two_solutions = recovery(results, truths, reqs)
     lat_ms = np.array(lat) * 1e3
     rl = roofline(pt_evals * FLOP_STATIC_PT, avg_kernel_s, kname, launches,
-                  counter_summary("counters_sa_kernel_static_surface.md", SA_SOURCES))
+                  counter_summary("counters_sa_kernel_static_surface.md", SA_SOURCES), units=pt_evals)
     rl["transcendentals_per_s"] = pt_evals * TRANS_STATIC_PT / avg_kernel_s
     out = {
         "metric": METRIC,

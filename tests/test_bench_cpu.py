@@ -28,6 +28,10 @@ def test_roofline_arithmetic():
     r = bench.roofline(1.0e12, 0.5, "k", 1, {"traffic_bytes_per_launch": 123, "valu_insts_per_simd_cycle": 0.2,
                                               "valu_busy_rocprof": 0.8, "file": "profiles/x.md"})
     assert r["traffic"] == 123 and r["valu_insts_per_simd_cycle"] == 0.2 and r["counters_from"] == "profiles/x.md"
+    assert "executed_fp32_tflops" not in r
+    r = bench.roofline(1.0e12, 0.5, "k", 1, {"executed_fp32_flops_per_unit": 20.0}, units=1e10)
+    assert r["executed_fp32_tflops"] == pytest.approx(20.0 * 1e10 / 0.5 / 1e12)
+    assert r["executed_fp32_frac"] == pytest.approx(r["executed_fp32_tflops"] / 157.3)
 
 
 @pytest.mark.parametrize("name,sources", [("counters_sa_kernel_static_surface.md", bench.SA_SOURCES),
@@ -40,6 +44,7 @@ def test_counter_summaries_match_the_committed_sources(name, sources):
     assert d is not None, name
     assert d["traffic_bytes_per_launch"] > 0
     assert 0 < d["valu_insts_per_simd_cycle"] < 1
+    assert d["executed_fp32_flops_per_unit"] > 0 and d["unit"]
 
 
 def test_counter_summary_dropped_when_sources_differ(tmp_path, monkeypatch):
