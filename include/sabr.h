@@ -134,8 +134,8 @@ enum { SABR_MC_PLAIN = 0, SABR_MC_ANTITHETIC = 1 };
 typedef struct {
     int64_t n_paths;
     int32_t steps_per_year;
-    int32_t scheme;
     uint64_t seed;
+    int32_t scheme;      /* last, so that an initialiser of the first three keeps the plain scheme */
 } sabr_mc;
 
 typedef struct {

@@ -59,7 +59,7 @@ class sabr_sa(C.Structure):
 
 
 class sabr_mc(C.Structure):
-    _fields_ = [("n_paths", C.c_int64), ("steps_per_year", C.c_int32), ("scheme", C.c_int32), ("seed", C.c_uint64)]
+    _fields_ = [("n_paths", C.c_int64), ("steps_per_year", C.c_int32), ("seed", C.c_uint64), ("scheme", C.c_int32)]
 
 
 class sabr_result(C.Structure):
