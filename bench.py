@@ -304,6 +304,33 @@ def bench_mc_calibration(S, inputs, ctx, args):
                                 "targets": "FP32 prices on the same 65536 common paths at the truth"}}
 
 
+def bench_surface_fp64(S, inputs, ctx, args):
+    """The static surface workload in FP64 mode (every formula evaluation in
+    double, the same fits, chains and iterations): one prepared batch, one
+    warm-up run and two timed ones."""
+    reqs, truths = build_requests(S, inputs, ctx, S.SABR_FP64)
+    batch = S.sabr_batch_prepare(ctx, reqs)
+    S.sabr_ctx_enable_timing(ctx, True)
+    S.sabr_batch_run(batch, raw=True)
+    S.sabr_ctx_timing(ctx, reset=True)
+    reps = 2
+    t = time.perf_counter()
+    for _ in range(reps):
+        S.sabr_batch_run(batch, raw=True)
+    wall = (time.perf_counter() - t) / reps
+    ms, n, name = S.sabr_ctx_timing(ctx, reset=True)
+    results = S.sabr_batch_run(batch)
+    S.sabr_batch_destroy(batch)
+    err, _ = recovery(results, truths, reqs)
+    pts = N_CHAINS * N_ITERS * sum(r.market.n_obs for r in reqs)
+    k_s = ms / 1e3 / max(n, 1)
+    return {"metric": "calibrations/s", "value": len(reqs) / wall, "unit": "calibrations/s",
+            "ms_per_step": wall * 1e3, "kernel": name, "avg_kernel_ms": k_s * 1e3,
+            "formula_evals_per_s": pts / k_s, "max_param_error_vs_exact_fit": err,
+            "config": {"workload": "static SABR surface as the default line, FP64 throughout (24 fits x 4096 "
+                                   "chains x 20000 iterations)"}}
+
+
 def bench_dynamic(S, inputs, ctx, args):
     """Dynamic SABR case I, joint fit of 20 maturities x 20 strikes, 5
     parameters, 8192 chains x `iters` iterations, FP32 bulk, polish."""
@@ -463,7 +490,8 @@ def bench_copy(S, inputs, ctx, args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", default="surface", choices=["surface", "mc_calibration", "dynamic", "serving", "copy"])
+    ap.add_argument("--workload", default="surface",
+                    choices=["surface", "surface_fp64", "mc_calibration", "dynamic", "serving", "copy"])
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--mc-iters", type=int, default=500)
     ap.add_argument("--dyn-iters", type=int, default=50000)
@@ -494,7 +522,7 @@ def main():
     ctx = S.sabr_ctx_create(0)
     if args.workload != "surface":
         fn = {"mc_calibration": bench_mc_calibration, "dynamic": bench_dynamic, "serving": bench_serving,
-              "copy": bench_copy}
+              "copy": bench_copy, "surface_fp64": bench_surface_fp64}
         out = fn[args.workload](S, inputs, ctx, args)
         out.update({"n_gpus": 1, "data": "synthetic", "higher_is_better": True})
         ctx.close()
@@ -573,13 +601,16 @@ def main():
     if not args.no_mc:
         out["mc_path_steps"] = mc_path_steps(S, ctx)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(reqs, results, args.cpu_sample_iters)
-        out["max_vol_error_fp32_vs_oracle"] = fp32_vs_oracle(S, ctx, reqs, results)
+        # the oracle leg: its timing, and its vols at the calibrated points
+        # against the library's FP32 vols there
+        cb = cpu_baseline(reqs, results, args.cpu_sample_iters)
+        cb["fp32_vols_max_abs_error"] = fp32_vs_oracle(S, ctx, reqs, results)
+        out["cpu_baseline"] = cb
     if not args.no_extra:
         print("static surface done; other configs follow", file=sys.stderr, flush=True)
         out["configs"] = {}
-        for name, fn in (("dynamic", bench_dynamic), ("mc_calibration", bench_mc_calibration),
-                         ("serving", bench_serving)):
+        for name, fn in (("surface_fp64", bench_surface_fp64), ("dynamic", bench_dynamic),
+                         ("mc_calibration", bench_mc_calibration), ("serving", bench_serving)):
             out["configs"][name] = fn(S, inputs, ctx, args)
             print("%s done" % name, file=sys.stderr, flush=True)
     ctx.close()
