@@ -81,8 +81,12 @@ __global__ void __launch_bounds__(kWG, 3) sa_kernel(const ReqDesc *reqs, const i
     double *s_lb = reinterpret_cast<double *>(smem + sizeof(ArgminSmem));
     double *s_ub = s_lb + kMaxPar;
     Pt<R> *pts = reinterpret_cast<Pt<R> *>(smem + sizeof(ArgminSmem) + 2 * kMaxPar * sizeof(double));
-    Row<R> *rows = reinterpret_cast<Row<R> *>(reinterpret_cast<unsigned char *>(pts) + pts_bytes<R>(rq.n_pts));
-    stage_grid<R>(rq, P, Mt, pts, rows);
+    // wide lane groups take whole rows on different lanes at once: spare
+    // records between the rows spread their starts over the LDS banks
+    constexpr bool kRowPad = LPC > 2;
+    Row<R> *rows = reinterpret_cast<Row<R> *>(reinterpret_cast<unsigned char *>(pts) +
+                                              pts_bytes<R>(rq.n_pts + (kRowPad ? rq.n_mat : 0)));
+    stage_grid<R>(rq, P, Mt, pts, rows, kRowPad);
     if (threadIdx.x < NP) {
         s_lb[threadIdx.x] = rq.lb[threadIdx.x];
         s_ub[threadIdx.x] = rq.ub[threadIdx.x];
@@ -353,9 +357,10 @@ const void *atm_seed_kernel_ptr() { return (const void *)atm_seed_kernel; }
 const void *prepare_points_kernel_ptr() { return (const void *)prepare_points_kernel; }
 const void *prepare_mats_kernel_ptr() { return (const void *)prepare_mats_kernel; }
 
+// (room for one spare record per row, which the wide annealing kernels use)
 size_t grid_smem_bytes(bool fp32, int n_pts, int n_mat) {
-    return fp32 ? pts_bytes<float>(n_pts) + sizeof(Row<float>) * n_mat
-                : pts_bytes<double>(n_pts) + sizeof(Row<double>) * n_mat;
+    return fp32 ? pts_bytes<float>(n_pts + n_mat) + sizeof(Row<float>) * n_mat
+                : pts_bytes<double>(n_pts + n_mat) + sizeof(Row<double>) * n_mat;
 }
 size_t sa_smem_fixed_bytes() { return sizeof(ArgminSmem) + 2 * kMaxPar * sizeof(double); }
 

@@ -61,12 +61,39 @@ __device__ inline void normalise_point(double k, double f, double beta, int form
 }
 
 // Stage the points and rows of one request into LDS (all threads of the
-// block take part; the caller synchronises afterwards).
+// block take part; the caller synchronises afterwards).  With row_pad, a row
+// of even length is followed by one spare record, so that the rows' starts
+// fall on different LDS banks (lanes reading different rows at once then
+// conflict less: a 48-byte record is 12 banks wide, and a stride of an odd
+// number of records spreads 8 rows over distinct bank groups); the rows' p0
+// and p1 index the padded records.
 template <typename R>
 __device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const MatsD &Mt,
-                                  Pt<R> *pts, Row<R> *rows) {
+                                  Pt<R> *pts, Row<R> *rows, bool row_pad = false) {
+    for (int i = threadIdx.x; i < rq.n_mat; i += blockDim.x) {
+        const int g = rq.mat_off + i;
+        int shift = 0;
+        if (row_pad)
+            for (int k = 0; k < i; ++k)
+                shift += ((Mt.offs[rq.mat_off + k + 1] - Mt.offs[rq.mat_off + k]) & 1) == 0;
+        Row<R> r;
+        r.T = (R)Mt.T[g];
+        r.lnf = (R)Mt.lnf[g];
+        r.F1 = (R)Mt.F1[g];
+        r.pad = (R)0;
+        r.p0 = Mt.offs[g] - rq.pt_off + shift;
+        r.p1 = Mt.offs[g + 1] - rq.pt_off + shift;
+        r.q0 = r.q1 = 0;
+        rows[i] = r;
+    }
+    if (row_pad) __syncthreads();   // the points read their rows' padded starts
     for (int j = threadIdx.x; j < rq.n_pts; j += blockDim.x) {
         const int g = rq.pt_off + j;
+        int slot = j;
+        if (row_pad) {
+            const int r = P.row[g] - rq.mat_off;
+            slot = j + rows[r].p0 - (Mt.offs[rq.mat_off + r] - rq.pt_off);
+        }
         Pt<R> p;
         p.P1 = (R)P.P1[g];
         p.Z = (R)P.Z[g];
@@ -78,19 +105,7 @@ __device__ inline void stage_grid(const ReqDesc &rq, const PointsD &P, const Mat
         p.T = (R)Mt.T[P.row[g]];
         p.sw = (R)P.sw[g];
         p.tsw = (R)(P.target[g] * P.sw[g]);
-        pts[j] = p;
-    }
-    for (int i = threadIdx.x; i < rq.n_mat; i += blockDim.x) {
-        const int g = rq.mat_off + i;
-        Row<R> r;
-        r.T = (R)Mt.T[g];
-        r.lnf = (R)Mt.lnf[g];
-        r.F1 = (R)Mt.F1[g];
-        r.pad = (R)0;
-        r.p0 = Mt.offs[g] - rq.pt_off;
-        r.p1 = Mt.offs[g + 1] - rq.pt_off;
-        r.q0 = r.q1 = 0;
-        rows[i] = r;
+        pts[slot] = p;
     }
 }
 
