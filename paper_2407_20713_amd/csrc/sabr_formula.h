@@ -17,6 +17,7 @@ template <typename R>
 struct alignas(16) Row {
     R T, lnf, F1, pad;    // maturity, ln f, f^(1-beta) (beta fixed)
     int32_t p0, p1, q0, q1;
+    int32_t spare[4];     // 48 bytes in float: lanes reading consecutive rows at once meet fewer LDS banks
 };
 // The point records are followed by kPtPad spare records, so that the point
 // loops can read ahead past a row's end (the values read there are unused).
