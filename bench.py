@@ -395,25 +395,36 @@ def serving_requests(S, inputs, ctx, n, rate, seed, mc_paths):
 
 
 def serve(S, ctx, trace, reqs, rate_scale, max_slots, quantum):
-    """Submit each request at its (scaled) arrival time; returns latencies and the makespan."""
+    """Submit each request at its (scaled) arrival time; returns latencies (in
+    completion order), the kind of request each one belongs to, the makespan
+    and the server's statistics."""
     srv = S.Server(ctx, max_slots=max_slots, hbm_budget_bytes=8 << 30, quantum_levels=quantum)
     t0 = time.perf_counter()
-    lat, pending, i = [], 0, 0
+    lat, kind, pending, i = [], [], 0, 0
+    kind_of = {}
     while i < len(reqs) or pending:
         now = time.perf_counter() - t0
         while i < len(reqs) and trace[i].arrival_s * rate_scale <= now:
-            srv.submit(reqs[i])
+            kind_of[srv.submit(reqs[i])] = trace[i].kind
             i += 1
             pending += 1
         for t, res, l in srv.poll(256, 500):
             lat.append(l)
+            kind.append(kind_of.pop(t))
             pending -= 1
             if len(lat) % 200 == 0:
                 print("served %d / %d" % (len(lat), len(reqs)), file=sys.stderr, flush=True)
     span = time.perf_counter() - t0
     st = srv.stats()
     srv.close()
-    return np.array(lat), span, st
+    return np.array(lat), np.array(kind), span, st
+
+
+def latency_by_kind(lat, kind):
+    """p50 / p99 in ms of each kind of request present."""
+    return {k: {"requests": int(np.sum(kind == k)), "p50_ms": float(np.percentile(lat[kind == k], 50) * 1e3),
+                "p99_ms": float(np.percentile(lat[kind == k], 99) * 1e3)}
+            for k in ("static", "dynamic", "mc") if np.any(kind == k)}
 
 
 def bench_serving(S, inputs, ctx, args):
@@ -424,17 +435,18 @@ def bench_serving(S, inputs, ctx, args):
     sabr_calibrate call per request, first come first served."""
     n = args.serve_requests
     trace, reqs = serving_requests(S, inputs, ctx, n, 1.0, 0x5AB5, args.serve_paths)
-    lat_b, span_b, st_b = serve(S, ctx, trace, reqs, 0.0, args.serve_slots, args.serve_quantum)
+    lat_b, _, span_b, st_b = serve(S, ctx, trace, reqs, 0.0, args.serve_slots, args.serve_quantum)
     capacity = n / span_b
     tried = []
     for frac in (0.5, 0.35):
         rate = frac * capacity
-        lat_s, span_s, st_s = serve(S, ctx, trace, reqs, 1.0 / rate, args.serve_slots, args.serve_quantum)
+        lat_s, kind_s, span_s, st_s = serve(S, ctx, trace, reqs, 1.0 / rate, args.serve_slots, args.serve_quantum)
         offered = n / (trace[-1].arrival_s / rate)
         served = n / span_s
         tried.append({"fraction_of_capacity": frac, "offered_per_s": offered, "served_per_s": served,
                       "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
-                      "p99_ms": float(np.percentile(lat_s, 99) * 1e3)})
+                      "p99_ms": float(np.percentile(lat_s, 99) * 1e3),
+                      "by_kind": latency_by_kind(lat_s, kind_s)})
         if served >= 0.95 * offered:
             break
     nb = min(args.serve_baseline, n)
@@ -464,7 +476,8 @@ def bench_serving(S, inputs, ctx, args):
             "one_request_per_launch": {"requests": nb, "offered_per_s": last["offered_per_s"],
                                        "calibrations_per_s": nb / span_1,
                                        "p50_ms": float(np.percentile(lat_1, 50) * 1e3),
-                                       "p99_ms": float(np.percentile(lat_1, 99) * 1e3)}}
+                                       "p99_ms": float(np.percentile(lat_1, 99) * 1e3),
+                                       "by_kind": latency_by_kind(lat_1, np.array([t.kind for t in trace[:nb]]))}}
 
 
 def bench_copy(S, inputs, ctx, args):

@@ -90,3 +90,14 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode != 0 and "one GPU" in r.stderr
+
+
+def test_latency_by_kind():
+    """Serving latencies split by the kind of request, in milliseconds; kinds
+    absent from the trace are left out."""
+    lat = np.array([0.010, 0.020, 0.030, 1.0, 2.0])
+    kind = np.array(["static", "static", "static", "mc", "mc"])
+    d = bench.latency_by_kind(lat, kind)
+    assert set(d) == {"static", "mc"}
+    assert d["static"]["requests"] == 3 and d["static"]["p50_ms"] == pytest.approx(20.0)
+    assert d["mc"]["p99_ms"] == pytest.approx(1990.0)
