@@ -217,14 +217,17 @@ int stage_copy(sabr_server *s, void *dst, const void *src, size_t bytes) {
 
 // Temperature levels a formula slot advances per quantum.  A quantum lasts as
 // long as its slowest slot, so each slot takes as many levels as keep its work
-// within four full quanta of the largest static slot (41 strikes, two lanes
-// per chain), at least one and at most Q.  Work per iteration and lane, in
+// within eight full quanta of the largest static slot (41 strikes, two lanes
+// per chain), at least one and at most Q.  (Four made the largest dynamic
+// grids, 2 levels a quantum, the tail of the serving latency; sixteen makes
+// every quantum, and so the static requests and the Monte Carlo iterations
+// that start once per quantum, slower.)  Work per iteration and lane, in
 // point evaluations: static ceil(n_pts / 2) + 8 (proposal, random words,
 // Metropolis test), dynamic n_pts + 15 n_mat (the row blocks) + 10.  A
 // request's result does not depend on how its levels are cut into quanta.
 int slot_quantum_levels(int Q, int kind, int n_pts, int n_mat) {
     if (kind == KIND_MC) return Q;
-    const double ref = 4.0 * Q * (21 + 8);
+    const double ref = 8.0 * Q * (21 + 8);
     const double c = kind == KIND_STATIC ? (n_pts + 1) / 2 + 8 : n_pts + 15.0 * n_mat + 10;
     const int q = (int)(ref / c);
     return q < 1 ? 1 : (q > Q ? Q : q);
