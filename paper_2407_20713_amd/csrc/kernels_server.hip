@@ -222,10 +222,10 @@ __device__ __forceinline__ bool mc_slot_live(const SlotDev &s) {
     return s.kind == KIND_MC && (s.state == SLOT_READY || s.state == SLOT_RUNNING) && s.iter < s.sa.n_iters;
 }
 
-// Slots whose option count falls in LDS class `cls` (see mc_slot_class).
-__global__ void __launch_bounds__(64) mc_slot_crn_kernel(SlotDev *slots, int cls) {
+// Path block blockIdx.x % kMcPBlocks of Monte Carlo slot blockIdx.x / kMcPBlocks.
+__global__ void __launch_bounds__(64) mc_slot_crn_kernel(SlotDev *slots) {
     SlotDev &s = slots[blockIdx.x / kMcPBlocks];
-    if (!mc_slot_live(s) || mc_slot_class(s.crn.n_obs) != cls) return;
+    if (!mc_slot_live(s)) return;
     extern __shared__ unsigned char smem[];
     McCrnDesc d = s.crn;
     if (s.iter < 0) d.n_chains = 1;   // f(x0) from Y[0] = x0

@@ -12,13 +12,11 @@ constexpr int kSlotMaxPts = 1024;
 constexpr int kSlotMaxMat = 32;
 constexpr int kMcPBlocks = 128;     // path blocks of one Monte Carlo slot
 constexpr int kMcPriceGroups = 32;  // option groups of the per-slot price launch
-constexpr int kSlotMaxMcObs = 600;  // options of one Monte Carlo slot (LDS: 260 B each)
-// Monte Carlo slots are priced by one launch per LDS class, each sized for
-// the largest option count of its class, so that small grids keep several
-// waves per CU: class c holds option counts up to mc_class_obs(c).
-constexpr int kMcClasses = 3;
-__host__ __device__ constexpr int mc_class_obs(int c) { return c == 0 ? 96 : (c == 1 ? 256 : kSlotMaxMcObs); }
-__host__ __device__ inline int mc_slot_class(int n_obs) { return n_obs <= mc_class_obs(0) ? 0 : (n_obs <= mc_class_obs(1) ? 1 : 2); }
+// Options of one Monte Carlo slot.  Its path blocks add their sums straight
+// into HBM, so a block's LDS holds the normals and the strikes only (3.4 KB
+// at this maximum, far from limiting the waves per CU): one launch with
+// that LDS covers every Monte Carlo slot.
+constexpr int kSlotMaxMcObs = 600;
 
 // One slot of the serving table (device memory).  Pointers address the
 // request's own region of the server's arena; grid offsets are slot-local.

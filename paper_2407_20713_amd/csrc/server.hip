@@ -128,9 +128,7 @@ struct sabr_server {
     int n_slots = 0, n_mc = 0, Q = 1;
     hipStream_t stream = nullptr;      // uploads, formula slots, status
     hipStream_t stream_mc = nullptr;   // Monte Carlo slots (overlap the formula slots)
-    hipStream_t stream_cls[kMcClasses] = {};   // fork of the Monte Carlo graph, one per LDS class
     hipEvent_t ev_up = nullptr, ev_mc = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join[kMcClasses] = {};
     unsigned char *arena_dev = nullptr;
     Arena arena;
     SlotDev *d_slots = nullptr;
@@ -217,17 +215,17 @@ int stage_copy(sabr_server *s, void *dst, const void *src, size_t bytes) {
 
 // Temperature levels a formula slot advances per quantum.  A quantum lasts as
 // long as its slowest slot, so each slot takes as many levels as keep its work
-// within eight full quanta of the largest static slot (41 strikes, two lanes
-// per chain), at least one and at most Q.  (Four made the largest dynamic
-// grids, 2 levels a quantum, the tail of the serving latency; sixteen makes
-// every quantum, and so the static requests and the Monte Carlo iterations
-// that start once per quantum, slower.)  Work per iteration and lane, in
+// within four full quanta of the largest static slot (41 strikes, two lanes
+// per chain), at least one and at most Q.  (Eight gives the largest dynamic
+// grids more levels per quantum but makes every quantum, and so the static
+// requests and the Monte Carlo iterations that start once per quantum,
+// slower: a longer serving tail.)  Work per iteration and lane, in
 // point evaluations: static ceil(n_pts / 2) + 8 (proposal, random words,
 // Metropolis test), dynamic n_pts + 15 n_mat (the row blocks) + 10.  A
 // request's result does not depend on how its levels are cut into quanta.
 int slot_quantum_levels(int Q, int kind, int n_pts, int n_mat) {
     if (kind == KIND_MC) return Q;
-    const double ref = 8.0 * Q * (21 + 8);
+    const double ref = 4.0 * Q * (21 + 8);
     const double c = kind == KIND_STATIC ? (n_pts + 1) / 2 + 8 : n_pts + 15.0 * n_mat + 10;
     const int q = (int)(ref / c);
     return q < 1 ? 1 : (q > Q ? Q : q);
@@ -412,8 +410,8 @@ int capture_one(hipStream_t st, hipGraph_t *g, hipGraphExec_t *ge, F body) {
 // grids of new formula slots and advances every formula slot by Q
 // temperature levels in one launch of sa_slot_kernel; the formula status
 // graph copies those slots' states back.  The Monte Carlo graph (second
-// stream) runs one iteration of every Monte Carlo slot (paths for each LDS
-// class, prices, objectives, accept/propose) and copies their states back;
+// stream) runs one iteration of every Monte Carlo slot (paths, prices,
+// objectives, accept/propose) and copies their states back;
 // it runs beside the formula quanta and is relaunched when it has finished.
 int capture_graph(sabr_server *s) {
     int nmc = s->n_mc, nf = s->n_slots - s->n_mc;
@@ -441,17 +439,13 @@ int capture_graph(sabr_server *s) {
     });
     if (rc) return rc;
     return capture_one(s->stream_mc, &s->graph_mc, &s->gexec_mc, [&] {
-        // the path launches of the LDS classes are independent branches of the graph
-        bool ok = hipEventRecord(s->ev_fork, s->stream_mc) == hipSuccess;
-        for (int c = 0; c < kMcClasses; ++c) {
-            int cls = c;
-            void *a2[] = {&ds, &cls};
-            ok = ok && hipStreamWaitEvent(s->stream_cls[c], s->ev_fork, 0) == hipSuccess;
-            ok = ok && hipLaunchKernel(mc_slot_crn_kernel_ptr(), dim3(nmc * kMcPBlocks), dim3(64), a2,
-                                       mc_crn_smem_bytes(mc_class_obs(c), true), s->stream_cls[c]) == hipSuccess;
-            ok = ok && hipEventRecord(s->ev_join[c], s->stream_cls[c]) == hipSuccess;
-            ok = ok && hipStreamWaitEvent(s->stream_mc, s->ev_join[c], 0) == hipSuccess;
-        }
+        // a linear graph: its kernels stay on the Monte Carlo stream's own
+        // hardware queue (the parallel branches of a graph run on further
+        // queues, one of which the formula stream can share, and a formula
+        // quantum then waits behind a Monte Carlo kernel)
+        void *a2[] = {&ds};
+        bool ok = hipLaunchKernel(mc_slot_crn_kernel_ptr(), dim3(nmc * kMcPBlocks), dim3(64), a2,
+                                  mc_crn_smem_bytes(kSlotMaxMcObs, true), s->stream_mc) == hipSuccess;
         void *a3[] = {&ds};
         ok = ok && hipLaunchKernel(mc_slot_prices_kernel_ptr(), dim3(nmc, kMcPriceGroups), dim3(256), a3, 0,
                                    s->stream_mc) == hipSuccess;
@@ -645,11 +639,6 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
     ok = ok && hipStreamCreateWithFlags(&s->stream_mc, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&s->ev_up, hipEventDisableTiming) == hipSuccess;
     ok = ok && hipEventCreateWithFlags(&s->ev_mc, hipEventDisableTiming) == hipSuccess;
-    ok = ok && hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming) == hipSuccess;
-    for (int c = 0; c < kMcClasses; ++c) {
-        ok = ok && hipStreamCreateWithFlags(&s->stream_cls[c], hipStreamNonBlocking) == hipSuccess;
-        ok = ok && hipEventCreateWithFlags(&s->ev_join[c], hipEventDisableTiming) == hipSuccess;
-    }
     ok = ok && hipMalloc((void **)&s->arena_dev, budget) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->d_slots, sizeof(SlotDev) * max_slots) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->d_status, sizeof(SlotStatus) * max_slots) == hipSuccess;
@@ -807,11 +796,6 @@ int sabr_server_destroy(sabr_server *s) {
         if (g) hipGraphDestroy(g);
     if (s->ev_up) hipEventDestroy(s->ev_up);
     if (s->ev_mc) hipEventDestroy(s->ev_mc);
-    if (s->ev_fork) hipEventDestroy(s->ev_fork);
-    for (int c = 0; c < kMcClasses; ++c) {
-        if (s->ev_join[c]) hipEventDestroy(s->ev_join[c]);
-        if (s->stream_cls[c]) hipStreamDestroy(s->stream_cls[c]);
-    }
     if (s->arena_dev) hipFree(s->arena_dev);
     if (s->d_slots) hipFree(s->d_slots);
     if (s->d_status) hipFree(s->d_status);

@@ -152,9 +152,10 @@ def test_cancel_timeout_and_rejection(S, ctx, oracle):
 
 
 def test_monte_carlo_lds_classes_alone_equals_mix(S, ctx, oracle):
-    """Monte Carlo requests in each LDS class of the serving loop (up to 96,
-    256 and 600 options) give bitwise the same result alone and together
-    (for two quantum lengths)."""
+    """Monte Carlo requests of small, middle and large option counts (up to
+    96, 256 and 600 options, whose path blocks share one launch)
+    give bitwise the same result alone and together (for two quantum
+    lengths)."""
     reqs = []
     for k, (n_mat, n_k) in enumerate(((4, 15), (8, 25), (12, 41))):
         T = [0.25 * (i + 1) for i in range(n_mat)]
