@@ -312,13 +312,13 @@ int sabr_mc_cliquet(sabr_ctx *ctx, const sabr_problem *problem, double f0, doubl
  * A worker thread owns a device-resident table of max_slots slots.  A
  * submitted request waits in a queue (first come, first served within each
  * kind) until a slot of its kind is free and its device footprint (grid, schedule, chain state, Monte Carlo
- * partials) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each formula
+ * partials: 128 KiB per option) fits in the hbm_budget_bytes arena (0: 1 GiB).  Each formula
  * quantum replays a captured HIP graph that normalises new grids, advances
  * every formula slot by up to quantum_levels temperature levels (fewer for
  * slots whose grids make a level costly, so that one large request does not
  * stretch every quantum) and copies the slot states back; beside it, on a second stream, a second captured graph
- * advances every Monte Carlo slot by one iteration and is relaunched as soon
- * as it finishes.  Requests admitted while others run join at the next
+ * advances every Monte Carlo slot by one iteration and is relaunched at the
+ * first quantum boundary after it finishes.  Requests admitted while others run join at the next
  * launch.  Slots 0..max_slots/8-1 take Monte Carlo requests, the others
  * formula requests.
  *
@@ -326,7 +326,7 @@ int sabr_mc_cliquet(sabr_ctx *ctx, const sabr_problem *problem, double f0, doubl
  * Hagan formula (<= 256 chains), the dynamic case I formula (<= 512 chains)
  * or the static Monte Carlo objective (<= 64 chains, <= 600 options);
  * grids up to 1024 points and 32 maturities; Monte Carlo requests of at
- * most 32768 paths.  Others: SABR_E_INVAL (use sabr_calibrate).  A
+ * most 131072 paths.  Others: SABR_E_INVAL (use sabr_calibrate).  A
  * request's result depends only on the request (its
  * random words are keyed by its seed and chain ids, its sums run in a fixed
  * order): it is the same alone, in any mix and for any quantum length.
@@ -344,7 +344,7 @@ int sabr_server_create(sabr_ctx *ctx, int32_t max_slots, size_t hbm_budget_bytes
 /* Copies the request (the caller may free its arrays on return; mc may be
  * NULL for the formula objective) and queues it; *ticket identifies its
  * result.  Errors: SABR_E_INVAL (invalid or unsupported request, including a
- * Monte Carlo request of more than 32768 paths), SABR_E_BUDGET (larger than
+ * Monte Carlo request of more than 131072 paths), SABR_E_BUDGET (larger than
  * the whole budget). */
 int sabr_server_submit(sabr_server *srv, const sabr_market *market, const sabr_problem *problem,
                        const sabr_objspec *obj, const sabr_sa *sa, const sabr_mc *mc, uint64_t *ticket);

@@ -10,7 +10,7 @@ enum SlotKind : int32_t { KIND_STATIC = 0, KIND_DYN_I = 1, KIND_MC = 2 };
 constexpr int kSlotThreads = 512;   // one workgroup per formula slot
 constexpr int kSlotMaxPts = 1024;
 constexpr int kSlotMaxMat = 32;
-constexpr int kMcPBlocks = 128;     // path blocks of one Monte Carlo slot
+constexpr int kMcPBlocks = 512;     // path blocks of one Monte Carlo slot (16384 paths: 32 a block)
 constexpr int kMcPriceGroups = 32;  // option groups of the per-slot price launch
 // Options of one Monte Carlo slot.  Its path blocks add their sums straight
 // into HBM, so a block's LDS holds the normals and the strikes only (3.4 KB

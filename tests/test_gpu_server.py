@@ -258,16 +258,16 @@ def test_served_monte_carlo_request_follows_oracle(S, ctx, oracle):
 
 def test_served_monte_carlo_path_limit(S, ctx, oracle):
     """A served Monte Carlo request adds at most 256 payoffs per lane in
-    float: more than 256 x 128 paths is refused (sabr_calibrate takes it)."""
+    float: more than 256 x 512 paths is refused (sabr_calibrate takes it)."""
     g = inputs.make_grid([0.25], [np.exp(np.linspace(-0.2, 0.2, 3))], f0=1.0)
     lb, ub = inputs.box(inputs.STATIC)
     srv = S.Server(ctx, max_slots=16, quantum_levels=3)
     req = S.Request(S.Market.from_grid(g, target=np.full(3, 0.05)), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
                     kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=8,
-                    n_iters=4, seed=3, n_paths=32769, steps_per_year=50, mc_seed=1)
+                    n_iters=4, seed=3, n_paths=131073, steps_per_year=50, mc_seed=1)
     with pytest.raises(S.SabrError) as e:
         srv.submit(req)
     assert e.value.code == S.SABR_E_INVAL
-    req.mc.n_paths = 32768
+    req.mc.n_paths = 131072
     srv.submit(req)
     srv.close()
