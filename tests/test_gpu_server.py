@@ -256,6 +256,35 @@ def test_served_monte_carlo_request_follows_oracle(S, ctx, oracle):
     assert abs(res["f"] - ref["f"]) <= 1e-3 * ref["f"]
 
 
+def test_served_monte_carlo_at_the_path_limit(S, ctx, oracle):
+    """A served Monte Carlo request of 131072 paths, the most a slot takes
+    (512 path blocks of 256 paths: each lane adds 256 payoffs in float).  Its
+    objective at the parameters it returns is the oracle's FP64 objective on
+    the same common paths, within what a price error of 5e-5 relative plus
+    1e-7 allows (the float path scheme's bound in the price parity tests):
+    |f32 - f| <= sum_i (2 |e_i| d_i + d_i^2) w_i."""
+    g = inputs.make_grid([0.25, 0.5], [np.exp(np.linspace(-0.2, 0.2, 3))] * 2, f0=1.0)
+    m = oracle.Market(g.T, g.fwd, g.offs, g.K, disc=g.disc)
+    n_paths, spy, mc_seed = 131072, 50, 777
+    tgt, _ = oracle.mc_prices(m, oracle.STATIC, [0.2, -0.3, 0.5], 0.7, n_paths, spy, mc_seed + 1)
+    m.target = tgt
+    lb, ub = inputs.box(inputs.STATIC)
+    req = S.Request(S.Market.from_grid(g, target=tgt), S.Problem(S.SABR_STATIC, 0.7, lb, ub),
+                    kind=S.SABR_OBJ_MC, weighting=S.SABR_W_RELATIVE, precision=S.SABR_FP32, n_chains=8,
+                    n_iters=4, seed=5, n_paths=n_paths, steps_per_year=spy, mc_seed=mc_seed)
+    srv = S.Server(ctx, max_slots=16, quantum_levels=3)
+    res = run_all(srv, [req])[0][0]
+    srv.close()
+    assert res["status"] == 0
+    x = np.asarray(res["x"][:3])
+    ref_f = oracle.objective_mc(m, oracle.STATIC, x, 0.7, n_paths, spy, mc_seed, weighting=oracle.RELATIVE)
+    price, _ = oracle.mc_prices(m, oracle.STATIC, x, 0.7, n_paths, spy, mc_seed)
+    d = 5e-5 * np.abs(price) + 1e-7
+    tol = float(np.sum((2 * np.abs(price - tgt) * d + d ** 2) / tgt ** 2))
+    say("served mc at the path limit", x, res["f"], "oracle", ref_f, "tol", tol)
+    assert np.isfinite(ref_f) and abs(res["f"] - ref_f) <= tol
+
+
 def test_served_monte_carlo_path_limit(S, ctx, oracle):
     """A served Monte Carlo request adds at most 256 payoffs per lane in
     float: more than 256 x 512 paths is refused (sabr_calibrate takes it)."""
