@@ -345,10 +345,8 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         // |P1 Z| / |L - lb| and the sign never has to be applied.  The
         // residual sqrt(w) (target - vol) is one fma,
         // tsw - (|P1 Z| sqrt(w) corr) / |L - lb|, with |P1 Z| sqrt(w) staged
-        // per point; residuals in float, their squares summed in float over a
-        // row (at most a few tens of points a lane: a relative error near
-        // 1e-6, far below that of the float vols) and the row sums in double
-        // (the sums that decide the Metropolis test).
+        // per point; residuals in float, their squares summed in double (the
+        // sums that decide the Metropolis test).
         // A vol that is not finite and positive makes the objective +inf.
         // Its sign is corr's: the other factors are |P1 Z| sqrt(w) and
         // 1 / |L - lb| (in the island P1, sqrt(w) and z / x, all positive),
@@ -370,7 +368,6 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
         const float iscale = aln * 0.693147180559945309f;
         float k0 = 0.0f, k1 = 0.0f, k2 = 0.0f;
         double acc_a = 0.0, acc_b = 0.0;
-        float ra = 0.0f, rb = 0.0f;
         int cmin = 0x7fffffff;
         auto resid = [&](const Pt<R> &p, float &e, float &corr, bool &isl) {
             const float zr = fmaf(noa, p.Z, -rh);
@@ -395,8 +392,8 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
                 if (ib) eb = island(pb, cb);
             }
             cmin = min(min(cmin, __float_as_int(ca)), __float_as_int(cb));
-            ra = fmaf(ea, ea, ra);
-            rb = fmaf(eb, eb, rb);
+            acc_a = fma((double)ea, (double)ea, acc_a);
+            acc_b = fma((double)eb, (double)eb, acc_b);
         };
         auto single = [&](const Pt<R> &p) {
             float e, c;
@@ -404,7 +401,7 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             resid(p, e, c, is);
             if (is) e = island(p, c);
             cmin = min(cmin, __float_as_int(c));
-            ra = fmaf(e, e, ra);
+            acc_a = fma((double)e, (double)e, acc_a);
         };
         for (int i = 0; i < n_mat; ++i) {
             const Row<R> rw = (i == 0 && have_r0) ? r0 : rows[i];
@@ -440,9 +437,6 @@ __device__ double objective(const P *y, const Pt<R> *pts, const Row<R> *rows, in
             } else if (j < rw.p1) {
                 single(a0);
             }
-            acc_a += (double)ra;
-            acc_b += (double)rb;
-            ra = rb = 0.0f;
         }
         const double acc = acc_a + acc_b;
         return (cmin > 0 && acc < __builtin_inf()) ? acc : __builtin_inf();

@@ -116,8 +116,7 @@ def test_static_objective_fp32(S, ctx, oracle, formula):
 @pytest.mark.parametrize("weighting", [0, 1])
 def test_static_objective_fp32_values(S, ctx, oracle, formula, weighting):
     """FP32 objective values without model output (the annealing's float
-    loop: vols and residuals in float, their squares summed in float over a
-    row and the row sums in double)
+    loop: vols and residuals in float, their squares summed in double)
     against the oracle's FP64
     objective, within what a vol error of delta = 2e-5 allows:
     |f32 - f| <= sum_i (2 |e_i| delta + delta^2) w_i + 1e-6 f.  Ragged rows
